@@ -1,0 +1,20 @@
+"""Plain FP64 CPU oracle for FRAM-RIR batched multi-channel RIR synthesis.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path
+(the HIP library and its Python binding) never imports, calls or links anything
+here, and nothing here imports the product.  The only module both sides share
+is the seeded synthetic-input generator, which holds none of the method's
+arithmetic.
+
+Modules
+-------
+philox   Philox-4xW-10 counter-based generator, written from its publication.
+cbrt     Correctly rounded FP64 cube root by exact integer arithmetic.
+framrir  The method itself: room scalars (Eq. 2, 5), image draws (Sec. III-B,
+         III-C, Eq. 3, 4, 6), band-limited rendering of Eq. 1 / Eq. 8, the
+         adjoint with the draws held fixed, and finite differences.
+
+Every function is slow and direct on purpose: there is no blocking, fusion or
+reordering beyond what the paper's definitions state.
+"""

@@ -1,0 +1,62 @@
+"""Pins of the oracle's adjoint (gradients with the draws held fixed, reading
+R-20) against FP64 central finite differences of the rendered loss."""
+import numpy as np
+
+from oracle import framrir as F
+
+
+def _setup(n_img=30, n_mic=3, rt60=0.12, fs=16000.0):
+    rng = np.random.default_rng(5)
+    centre = np.array([2.1, 1.7, 1.3])
+    mics = centre + rng.normal(0, 0.04, size=(n_mic, 3))
+    room = F.Room(size=(4.0, 3.5, 2.8), rt60=rt60, fs=fs, c=343.0, seed=9,
+                  src=np.array([[0.9, 2.6, 1.1]]), mic=mics)
+    plan = F.room_plan(room, F.Params(img_lo=n_img, img_hi=n_img))
+    out = F.render_room(plan, room)
+    target = F.render_room(plan, room, mic=mics + rng.normal(0, 0.01, size=mics.shape),
+                           r=plan["r"] + 0.05)
+    return room, plan, out, target
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def test_adjoint_matches_finite_differences():
+    room, plan, out, target = _setup()
+    _, grad_h = F.l2_loss(out, target)
+    gm, gs, gr = F.adjoint_room(plan, room, grad_h)
+    fm, fs_, fr = F.fd_grads(plan, room, target, step=1e-6)
+    assert _rel(gm, fm) < 1e-6
+    assert _rel(gs, fs_) < 1e-6
+    assert abs(gr - fr) / abs(fr) < 1e-6
+
+
+def test_finite_differences_converge():
+    # two step sizes agree: the loss is C^1 in the positions because P and P'
+    # vanish at the edge of the 81-tap footprint
+    room, plan, out, target = _setup(n_img=10, n_mic=2)
+    a = F.fd_grads(plan, room, target, step=1e-5)
+    b = F.fd_grads(plan, room, target, step=1e-6)
+    assert _rel(a[0], b[0]) < 1e-6 and _rel(a[1], b[1]) < 1e-6
+
+
+def test_adjoint_linear_in_upstream_gradient():
+    room, plan, out, target = _setup(n_img=20, n_mic=2)
+    rng = np.random.default_rng(1)
+    g1 = rng.normal(size=out.shape)
+    g2 = rng.normal(size=out.shape)
+    a = F.adjoint_room(plan, room, g1)
+    b = F.adjoint_room(plan, room, g2)
+    c = F.adjoint_room(plan, room, 2.0 * g1 - 3.0 * g2)
+    assert np.allclose(c[0], 2 * a[0] - 3 * b[0], rtol=1e-12, atol=1e-12)
+    assert np.isclose(c[2], 2 * a[2] - 3 * b[2], rtol=1e-12)
+
+
+def test_pulse_derivative_matches_difference_quotient():
+    x = np.linspace(-40.49, 40.49, 4001)
+    h = 1e-6
+    fd = (F.pulse(x + h) - F.pulse(x - h)) / (2 * h)
+    assert np.max(np.abs(F.pulse_deriv(x) - fd)) < 1e-8
+    # C^1 at the footprint edge
+    assert abs(F.pulse(40.5)) < 1e-15 and abs(F.pulse_deriv(40.4999999)) < 1e-9
