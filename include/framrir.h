@@ -1,0 +1,232 @@
+/*
+ * framrir.h - C ABI of the MI355X (gfx950) FRAM-RIR library.
+ *
+ * FRAM-RIR (Luo & Gu, arXiv 2304.08052) approximates the image-source RIR of
+ * Eq. 1 by sampling, per source, I virtual sources: their distance ratio from
+ * the quadratic density of Eq. 3 rescaled by Eq. 4, a direction uniform in
+ * azimuth and elevation (Sec. III-B), and a fractional reflection count from
+ * Eq. 6.  Every (virtual source, microphone) pair then adds r^g / D times a
+ * pulse at delay D fs / c0 to that microphone's RIR (Eq. 1, Eq. 8).  Here the
+ * pulse is an 81-tap Hann-windowed sinc at the output rate, so delays stay
+ * fractional.
+ *
+ * Flow
+ *   1. framrir_plan_create      host only: validates the batch, computes the
+ *                               per-room and per-source scalars (Eq. 2, Eq. 5,
+ *                               the image counts I) and a device descriptor
+ *                               blob, and splits the work into items.
+ *   2. the caller copies the blob (framrir_plan_desc) to device memory.
+ *   3. framrir_draw             device: one row per virtual source, the
+ *                               sampled position and reflection count.
+ *   4. framrir_render           device: RIRs from the image table.
+ *      framrir_render_backward  device: gradients of a loss through the render,
+ *                               with the image table held fixed.
+ *
+ * Conventions
+ *   - Every function returns 0 (FRAMRIR_OK) or a negative FRAMRIR_E_* code;
+ *     framrir_last_error_detail gives a message for the calling thread.  No
+ *     C++ exception crosses the ABI.  On error nothing is enqueued.
+ *   - Pointers named *_dev are device pointers, all others host pointers.
+ *     The caller owns every buffer.  Device functions only enqueue work on
+ *     the given stream (a hipStream_t passed as void*; NULL = default stream):
+ *     they never synchronise, allocate or copy from the host, so they can be
+ *     captured into a hipGraph.  Asynchronous faults surface at the caller's
+ *     next synchronisation.
+ *   - Positions, room sizes, T60, fs, c0 and r are FP64; RIRs and gradients
+ *     are FP32.
+ *   - Rooms are indexed b in [0, B); their sources and microphones are stored
+ *     back to back: source j of room b is row src_off[b] + j of a
+ *     [sum n_src, 3] array, and likewise for microphones.
+ *   - Output layout ("ragged packed"): the RIRs of room b start at float
+ *     offset out_off[b] and are laid out [n_src][n_mic][T_b] (row-major).
+ *     Every output sample is written, so the buffer need not be cleared.
+ *   - Image table: one row of 4 doubles (x, y, z, g) per virtual source,
+ *     sources back to back (img_off per source).  Row 0 of every source is
+ *     the direct path (position = source, g = 0, Sec. III-D); rows 1..I are
+ *     the sampled virtual sources.
+ */
+#ifndef FRAMRIR_H
+#define FRAMRIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FRAMRIR_OK 0
+#define FRAMRIR_E_INVALID_ARG (-1) /* null pointer, count <= 0, non-finite value */
+#define FRAMRIR_E_GEOMETRY (-2)    /* room size <= 0, point not strictly inside, D = 0, d0 >= c0 T60 */
+#define FRAMRIR_E_RANGE (-3)       /* T60, fs, c0 <= 0; r not in (0,1); parameter out of range */
+#define FRAMRIR_E_WORKSPACE (-4)   /* workspace or buffer too small */
+#define FRAMRIR_E_DEVICE (-5)      /* HIP error while enqueueing */
+#define FRAMRIR_E_UNSUPPORTED (-6) /* device is not gfx950, or unsupported option */
+
+/* One room (Sec. II): shoebox size, reverberation time, sample rate, sound
+ * speed and the seed of its counter-based draws.  r_override: reflection
+ * coefficient to use instead of Eq. 2 (NaN = Eq. 2 as printed). */
+typedef struct framrir_room {
+    double size[3];    /* Lx, Ly, Lz in metres, > 0 */
+    double rt60;       /* T60 in seconds, > 0 */
+    double fs;         /* output sample rate in Hz, > 0 */
+    double c;          /* sound speed c0 in m/s, > 0 */
+    double r_override; /* NaN, or r in (0, 1) */
+    uint64_t seed;     /* Philox key: (seed & 0xffffffff, seed >> 32) */
+    int32_t n_src;     /* >= 1 */
+    int32_t n_mic;     /* >= 1, <= FRAMRIR_MAX_MICS */
+} framrir_room;
+
+#define FRAMRIR_MAX_MICS 64
+#define FRAMRIR_TAPS 81
+
+/* Free constants of the method, which the paper names but does not fix:
+ * alpha, beta of Eq. 3 (0 <= alpha < beta <= 1), a <= b of the perturbation
+ * p ~ U(a, b) in Eq. 6, tau of Eq. 6 (0.25, 0.5 or 1), and the range of the
+ * per-source image count I ~ U_int[img_lo, img_hi] (0 <= img_lo <= img_hi
+ * <= 65535).  taps must be 81.  flags must be 0. */
+typedef struct framrir_params {
+    double alpha, beta, a, b, tau;
+    int32_t img_lo, img_hi;
+    int32_t taps;
+    uint32_t flags;
+} framrir_params;
+
+/* Launch shape of the render and backward kernels (not part of the method):
+ * lds_bytes  LDS accumulator budget per workgroup (4096 .. 160000),
+ * wg_threads threads per workgroup (64 .. 1024, multiple of 64),
+ * grid_wgs   workgroups of the persistent render grid (0 = one per work item
+ *            up to 256 * floor(160000 / lds_bytes)).
+ * A time tile holds tile_len = floor(lds_bytes / 4 / m_group) - 160 samples
+ * of m_group microphones. */
+typedef struct framrir_launch {
+    int32_t lds_bytes;
+    int32_t wg_threads;
+    int32_t grid_wgs;
+    int32_t max_mic_group; /* microphones per work item, 1 .. 16 (0 = 8) */
+} framrir_launch;
+
+/* Sizes of a plan. */
+typedef struct framrir_plan_info {
+    int32_t n_rooms;
+    int32_t n_src;         /* sum over rooms of n_src */
+    int32_t n_mic;         /* sum over rooms of n_mic */
+    int32_t n_items;       /* render work items */
+    int64_t n_img;         /* rows of the image table: sum over sources of I + 1 */
+    int64_t out_floats;    /* floats of the ragged packed output */
+    int64_t desc_bytes;    /* size of the device descriptor blob */
+    int64_t ws_bytes;      /* workspace for framrir_render */
+    int64_t ws_bwd_bytes;  /* workspace for framrir_render_backward */
+    int32_t max_T;         /* longest RIR */
+    int32_t max_img;       /* largest I + 1 */
+} framrir_plan_info;
+
+typedef struct framrir_plan framrir_plan; /* opaque, host memory */
+
+/* Plans a batch (host only; Sec. II, III-A, III-C, Eq. 2, 5).
+ * rooms[n_rooms]; src: [sum n_src, 3] FP64 host; mic: [sum n_mic, 3] FP64
+ * host.  prm and launch may be NULL for the defaults (alpha 0.25, beta 1,
+ * a -2, b 2, tau 0.25, I in [1024, 4096]; lds 131072 B, 256 threads).
+ * Per room: T = ceil(T60 fs); R = V / S; r from Eq. 2 unless overridden;
+ * centre = mean microphone.  Per source: d0 = |src - centre|,
+ * RR_max = max(1, (log10 c0T60 - log10 d0 - 3) / log10 r), and
+ * I = img_lo + ((w * (img_hi - img_lo + 1)) >> 32) from the first Philox word
+ * w of counter (0, s, 1, 0).  Errors: INVALID_ARG, GEOMETRY, RANGE.
+ * On success *out owns host memory; free it with framrir_plan_destroy. */
+int framrir_plan_create(const framrir_room* rooms, int32_t n_rooms, const framrir_params* prm,
+                        const framrir_launch* launch, const double* src, const double* mic,
+                        framrir_plan** out);
+void framrir_plan_destroy(framrir_plan* plan);
+int framrir_plan_get_info(const framrir_plan* plan, framrir_plan_info* info);
+
+/* Copies per-room and per-source arrays of a plan into caller buffers (any
+ * pointer may be NULL): T[n_rooms], out_off[n_rooms + 1] (out_off[n_rooms] =
+ * out_floats), r[n_rooms] (the coefficient used by the draws), n_img[n_src]
+ * (I + 1 rows per source), img_off[n_src + 1], rrmax[n_src], d0[n_src]. */
+int framrir_plan_get_arrays(const framrir_plan* plan, int32_t* T, int64_t* out_off, double* r,
+                            int32_t* n_img, int64_t* img_off, double* rrmax, double* d0);
+
+/* Host pointer to the descriptor blob (owned by the plan, desc_bytes long),
+ * to be copied to 256-byte aligned device memory before the device calls. */
+const void* framrir_plan_desc(const framrir_plan* plan);
+
+/* Draw stage (Sec. III-B, III-C; Eq. 3, 4, 6).  Fills table_dev
+ * [n_img][4] FP64 with (x, y, z, g) per virtual source.  For sampled row
+ * i >= 1 of source s of room b, the words (w0..w3) = Philox4x32-10 of
+ * counter (i - 1, s, 0, 0) under key(seed_b) give u_k = (w_k + 1/2) 2^-32 and
+ *   theta = 2 pi u0, phi = pi (u1 - 1/2),
+ *   xhat  = cbrt(alpha^3 + u2 (beta^3 - alpha^3))   correctly rounded,
+ *   DR = 1 + (xhat - alpha) / (beta - alpha) (c0T60/d0 - 1),  D = d0 DR,
+ *   p = a + u3 (b - a),
+ *   g = clamp(1 + (D / c0T60)^2 (RR_max - 1) + p DR^tau, 1, RR_max),
+ *   position = centre + D (cos phi cos theta, cos phi sin theta, sin phi),
+ * every FP64 step rounded separately, so g is bit-identical to a sequential
+ * IEEE evaluation.  aux_dev (may be NULL): [n_img][8] FP64 debug rows
+ * (theta, phi, xhat, p, DR, D, g, 0); words_dev (may be NULL): [n_img][4]
+ * uint32 Philox words (zero for the direct-path row). */
+int framrir_draw(const framrir_plan* plan, const void* desc_dev, double* table_dev, double* aux_dev,
+                 uint32_t* words_dev, void* stream);
+
+/* Render (Eq. 1, Eq. 8).  For every source s, microphone m and table row i:
+ * D = |pos_i - mic_m|, t = D fs / c0, A = r^g_i / D, and
+ *   out[n] += A * P(n - t),  n = floor(t + 1/2) - 40 .. + 40, 0 <= n < T,
+ *   P(x) = sinc(x) (1 + cos(2 pi x / 81)) / 2.
+ * mic_dev [n_mic][3] and src_dev [n_src][3] FP64: positions to render with
+ * (row 0 of each source is taken from src_dev, the other rows from the
+ * table).  r_dev [n_rooms] FP64 or NULL (= the plan's r).  out_dev:
+ * out_floats FP32, 16-byte aligned.  ws_dev: ws_bytes of device memory,
+ * 256-byte aligned, contents need not be initialised.  Errors: INVALID_ARG,
+ * WORKSPACE, DEVICE. */
+int framrir_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                   const double* mic_dev, const double* src_dev, const double* r_dev,
+                   float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Draw and render in one call (table_dev as for framrir_draw). */
+int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                    const double* mic_dev, const double* src_dev, const double* r_dev,
+                    float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Adjoint of framrir_render with the table held fixed.  grad_out_dev: dL/dh
+ * in the output layout (FP32).  With u = (pos_i - mic_m) / D,
+ * S0 = sum_n dL/dh[n] P(n - t) and S1 = sum_n dL/dh[n] P'(n - t):
+ *   dL/dmic_m = sum_i u (A / D S0 + A fs / c0 S1)        -> grad_mic_dev [n_mic][3]
+ *   dL/dsrc_s = -(the same sum over row 0 only)          -> grad_src_dev [n_src][3]
+ *   dL/dr_b   = sum_{s,m,i} (g_i / r) A S0                -> grad_r_dev [n_rooms]
+ * Outputs are FP32 and fully overwritten; any may be NULL.  Sums run in a
+ * fixed order, so results are bitwise reproducible.  ws_dev: ws_bwd_bytes. */
+int framrir_render_backward(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                            const double* mic_dev, const double* src_dev, const double* r_dev,
+                            const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
+                            float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) of n counters: ctr_dev [n][4],
+ * key_dev [n][2], out_dev [n][4] (uint32, device).  Test export of the
+ * generator the draw stage uses. */
+int framrir_philox4x32(const uint32_t* ctr_dev, const uint32_t* key_dev, uint32_t* out_dev,
+                       int64_t n, void* stream);
+
+/* Correctly rounded cube root of n finite non-negative doubles (device
+ * buffers): the inverse-CDF step of Eq. 3.  Test export. */
+int framrir_cbrt_rn(const double* x_dev, double* y_dev, int64_t n, void* stream);
+
+/* Host (CPU) builds of the same draw-stage numerics as the device code:
+ * correctly rounded cube root and square root of positive normal doubles,
+ * and Philox4x32-10.  Test exports for machines without a GPU; host
+ * buffers. */
+int framrir_host_cbrt_rn(const double* x, double* y, int64_t n);
+int framrir_host_sqrt_rn(const double* x, double* y, int64_t n);
+int framrir_host_philox4x32(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n);
+
+/* Message for the last error on the calling thread (NUL-terminated, may be
+ * truncated to n bytes).  Returns the length of the full message. */
+int framrir_last_error_detail(char* buf, size_t n);
+const char* framrir_strerror(int code);
+
+/* Library version, (major << 16) | minor. */
+int framrir_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRAMRIR_H */

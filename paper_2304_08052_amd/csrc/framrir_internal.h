@@ -1,0 +1,265 @@
+// Internal layout of the FRAM-RIR device descriptor blob and the numeric
+// helpers shared by the host planner and the gfx950 kernels of this library.
+//
+// Everything in the blob is 8-byte aligned plain data.  The host planner
+// (plan.cpp) writes it; the kernels (kernels.hip) read it.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define FR_HD __host__ __device__ inline
+#else
+#define FR_HD inline
+#endif
+
+namespace framrir {
+
+constexpr int kTaps = 81;
+constexpr int kHalf = 40;          // taps are k - 40 .. k + 40 around k = floor(t + 1/2)
+constexpr int kHalo = 80;          // LDS guard samples on each side of a time tile
+constexpr int kListCap = 4096;     // compacted image indices per pass of a tile
+constexpr int kMaxMicGroup = 16;   // microphones per work item
+constexpr int kPartialStride = 3 * kMaxMicGroup + 4;   // backward partials per item
+
+enum TauCode : int32_t { kTauQuarter = 0, kTauHalf = 1, kTauOne = 2 };
+
+struct DescHeader {
+    int32_t n_rooms, n_src, n_mic, n_items;
+    int64_t n_img, out_floats;
+    int64_t room_bytes, src_bytes, item_bytes, room_items_bytes;   // byte offsets in the blob
+    double alpha, beta, a, b;
+    double a3, b3;             // alpha^3 and beta^3, each product rounded separately
+    double beta_minus_alpha, b_minus_a;
+    int32_t tau_code;
+    int32_t max_img;           // largest I + 1 of the batch
+    int32_t max_T;
+    int32_t pad0;
+};
+
+struct RoomDesc {
+    double fs_over_c;          // fs / c0
+    double r;                  // reflection coefficient of the draws (Eq. 2 or override)
+    double centre[3];          // mean microphone (sphere centre of Sec. III-B)
+    int64_t out_off;           // first float of the room in the packed output
+    int32_t T, n_src, n_mic;
+    int32_t src0, mic0;        // first global source / microphone row
+    int32_t item0, n_item;     // range in room_items
+    int32_t pad0;
+};
+
+struct SrcDesc {
+    double d0, q, ct, rrmax;   // |src - centre|, c0T60 / d0, c0T60, RR_max (Eq. 5)
+    double pos[3];             // source position used by the draws
+    uint32_t key0, key1;       // Philox key from the room seed
+    int32_t room, s_local;
+    int32_t n_img;             // I + 1 rows (row 0 = direct path)
+    int32_t pad0;
+    int64_t img_off;           // first row in the image table
+};
+
+struct WorkItem {
+    int32_t src;               // global source index
+    int32_t mic0;              // first microphone of the group (room-local)
+    int32_t n_mic;             // microphones in the group
+    int32_t t0;                // first output sample of the tile
+    int32_t len;               // samples of the tile (the last tile may reach past T)
+    int32_t full;              // 1 if the tile covers [0, T): every image is in range
+    int32_t pad0, pad1;
+};
+
+FR_HD const DescHeader* hdr(const void* blob) { return reinterpret_cast<const DescHeader*>(blob); }
+FR_HD const RoomDesc* rooms(const void* blob) {
+    return reinterpret_cast<const RoomDesc*>(reinterpret_cast<const char*>(blob) + hdr(blob)->room_bytes);
+}
+FR_HD const SrcDesc* srcs(const void* blob) {
+    return reinterpret_cast<const SrcDesc*>(reinterpret_cast<const char*>(blob) + hdr(blob)->src_bytes);
+}
+FR_HD const WorkItem* items(const void* blob) {
+    return reinterpret_cast<const WorkItem*>(reinterpret_cast<const char*>(blob) + hdr(blob)->item_bytes);
+}
+FR_HD const int32_t* room_items(const void* blob) {
+    return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(blob) + hdr(blob)->room_items_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Round: multiply words 0
+// and 2 by M0, M1 into 64-bit products; new state (hi(M1 x2) ^ x1 ^ k0,
+// lo(M1 x2), hi(M0 x0) ^ x3 ^ k1, lo(M0 x0)); the key advances by the Weyl
+// increments between rounds.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+FR_HD void philox4x32_10(uint32_t x[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * x[0];
+        const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * x[2];
+        const uint32_t y0 = static_cast<uint32_t>(p1 >> 32) ^ x[1] ^ k0;
+        const uint32_t y1 = static_cast<uint32_t>(p1);
+        const uint32_t y2 = static_cast<uint32_t>(p0 >> 32) ^ x[3] ^ k1;
+        const uint32_t y3 = static_cast<uint32_t>(p0);
+        x[0] = y0;
+        x[1] = y1;
+        x[2] = y2;
+        x[3] = y3;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bit-level FP64 helpers.
+// ---------------------------------------------------------------------------
+FR_HD uint64_t dbits(double x) {
+    union { double d; uint64_t u; } v;
+    v.d = x;
+    return v.u;
+}
+FR_HD double bitsd(uint64_t u) {
+    union { double d; uint64_t u; } v;
+    v.u = u;
+    return v.d;
+}
+FR_HD double next_up(double x) { return bitsd(dbits(x) + 1); }      // x > 0 finite
+FR_HD double next_down(double x) { return bitsd(dbits(x) - 1); }    // x > 0, not the smallest
+
+FR_HD uint64_t mul64hi(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return static_cast<uint64_t>((static_cast<unsigned __int128>(a) * b) >> 64);
+#endif
+}
+
+FR_HD double fma_d(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_fma(a, b, c);
+#else
+    return __builtin_fma(a, b, c);
+#endif
+}
+
+// Correctly rounded square root of a positive normal double.  The hardware
+// sequence gives a value within one ulp; the Tuckerman test then moves it to
+// the nearest double: y is RN(sqrt(x)) iff y (y - ulp-) < x <= y (y + ulp+),
+// each product compared with x exactly through the sign of one FMA.
+FR_HD double sqrt_rn(double x) {
+    double y = __builtin_sqrt(x);
+#pragma unroll 1
+    for (int it = 0; it < 4; ++it) {
+        const double up = next_up(y);
+        if (fma_d(y, up, -x) < 0.0) {          // x > y * next_up(y): y too small
+            y = up;
+            continue;
+        }
+        const double dn = next_down(y);
+        if (fma_d(y, dn, -x) >= 0.0) {         // x <= y * next_down(y): y too large
+            y = dn;
+            continue;
+        }
+        break;
+    }
+    return y;
+}
+
+// Sign of a - ((2Y + 1) 2^(e - 1))^3 for a = A 2^ea, the cube of the midpoint
+// between y = Y 2^e (Y a 53-bit integer) and its successor, compared exactly
+// in 256-bit integer arithmetic.  Returns +1, 0 or -1.
+FR_HD int cmp_cube_midpoint(uint64_t A, int ea, uint64_t Y, int e) {
+    const uint64_t N = 2 * Y + 1;                      // < 2^54
+    // N^3 as limbs c0..c2 (little endian)
+    const uint64_t sq_lo = N * N, sq_hi = mul64hi(N, N);   // N^2 < 2^108
+    const uint64_t t0 = sq_lo * N, t1 = mul64hi(sq_lo, N); // sq_lo * N
+    const uint64_t u0 = sq_hi * N, u1 = mul64hi(sq_hi, N); // sq_hi * N (<< 64)
+    uint64_t c[4];
+    c[0] = t0;
+    c[1] = t1 + u0;
+    c[2] = u1 + (c[1] < t1 ? 1u : 0u);
+    c[3] = 0;
+    // A * 2^(ea - 3(e - 1)) against N^3 * 2^0, or N^3 shifted when negative
+    const int s = ea - 3 * (e - 1);
+    uint64_t l[4] = {0, 0, 0, 0};
+    uint64_t r[4] = {c[0], c[1], c[2], c[3]};
+    if (s >= 0) {
+        if (s >= 256) return 1;
+        const int w = s >> 6, b = s & 63;
+        l[w] = A << b;
+        if (b != 0 && w + 1 < 4) l[w + 1] = A >> (64 - b);
+        if (w + 1 < 4 && b == 0) l[w + 1] = 0;
+    } else {
+        const int t = -s;
+        if (t >= 96) return -1;                        // N^3 << t exceeds 2^256 > A
+        const int w = t >> 6, b = t & 63;
+        uint64_t sh[4] = {0, 0, 0, 0};
+        for (int k = 3; k >= 0; --k) {
+            const int src = k - w;
+            uint64_t v = 0;
+            if (src >= 0) {
+                v = c[src] << b;
+                if (b != 0 && src - 1 >= 0) v |= c[src - 1] >> (64 - b);
+            }
+            sh[k] = v;
+        }
+        for (int k = 0; k < 4; ++k) r[k] = sh[k];
+        l[0] = A;
+    }
+    for (int k = 3; k >= 0; --k) {
+        if (l[k] > r[k]) return 1;
+        if (l[k] < r[k]) return -1;
+    }
+    return 0;
+}
+
+// 53-bit integer mantissa and exponent of a positive normal double:
+// x = M 2^e with 2^52 <= M < 2^53.
+FR_HD void decompose(double x, uint64_t* M, int* e) {
+    const uint64_t u = dbits(x);
+    *M = (u & ((uint64_t(1) << 52) - 1)) | (uint64_t(1) << 52);
+    *e = static_cast<int>((u >> 52) & 0x7FF) - 1075;
+}
+
+// Correctly rounded cube root of a positive normal double (the inverse CDF of
+// Eq. 3).  A float seed refined by two FP64 Newton steps lands within an ulp;
+// exact midpoint comparisons then pick the nearest double.
+FR_HD double cbrt_rn(double a) {
+    uint64_t A;
+    int ea;
+    decompose(a, &A, &ea);
+    // scale a into [1, 8) by a multiple of 3 in the exponent
+    const int eb = ea + 52;                            // a = (A / 2^52) 2^eb, A/2^52 in [1, 2)
+    int q3 = eb >= 0 ? eb / 3 : -((-eb + 2) / 3);      // floor(eb / 3)
+    const double m = bitsd((dbits(a) & ~(uint64_t(0x7FF) << 52)) |
+                           (uint64_t(1023 + (eb - 3 * q3)) << 52));   // in [1, 8)
+    double y = static_cast<double>(cbrtf(static_cast<float>(m)));
+    y = y - (y * y * y - m) / (3.0 * y * y);
+    y = y - (y * y * y - m) / (3.0 * y * y);
+    y = y * bitsd(uint64_t(1023 + q3) << 52);          // exact power-of-two scaling
+#pragma unroll 1
+    for (int it = 0; it < 6; ++it) {
+        uint64_t Y;
+        int ey;
+        decompose(y, &Y, &ey);
+        if (cmp_cube_midpoint(A, ea, Y, ey) > 0) {     // a above the upper midpoint
+            y = next_up(y);
+            continue;
+        }
+        const double yd = next_down(y);
+        decompose(yd, &Y, &ey);
+        if (cmp_cube_midpoint(A, ea, Y, ey) < 0) {     // a below the lower midpoint
+            y = yd;
+            continue;
+        }
+        break;
+    }
+    return y;
+}
+
+}  // namespace framrir

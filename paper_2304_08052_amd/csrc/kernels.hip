@@ -1,0 +1,749 @@
+// gfx950 kernels of the FRAM-RIR library and their C-ABI launchers.
+//
+//   draw_kernel      Sec. III-B, III-C, Eq. 3, 4, 6: one thread per virtual
+//                    source; Philox4x32-10 words -> FP64 draws -> image table.
+//   render_kernel    Eq. 1, 8: persistent grid over work items (source,
+//                    microphone group, time tile); per (image, microphone) pair
+//                    an FP64 delay, then 81 windowed-sinc taps accumulated in an
+//                    LDS tile with ds_add_f32; coalesced writeback.
+//   backward_kernel  adjoint of the render with the image table held fixed:
+//                    per pair 81-tap dot products of dL/dh with P and P'.
+//   finalize_kernel  fixed-order reduction of the backward partials.
+//
+// Compiled with -ffp-contract=off: FP64 draw arithmetic is rounded one
+// operation at a time, in the order the method states.  FMAs in the render
+// are written explicitly.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "../../include/framrir.h"
+#include "framrir_internal.h"
+#include "plan_internal.h"
+
+using namespace framrir;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586;    // double nearest 2 pi
+constexpr double kPi = 3.141592653589793;       // double nearest pi
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr float kInvPiF = 0.318309886183790671538f;
+
+// ---- compile-time tap tables: cos(pi m / 81), sin(pi m / 81), m = -40..40,
+// from their Taylor series in FP64 (|pi m / 81| < 1.56, 16 terms).
+constexpr double ct_sin(double x) {
+    double term = x, sum = x;
+    for (int k = 1; k < 16; ++k) {
+        term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double ct_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 16; ++k) {
+        term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double kPiOver81 = 3.14159265358979323846 / 81.0;
+
+// ---------------------------------------------------------------------------
+// Draw stage
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) draw_kernel(const void* __restrict__ desc, double* __restrict__ table,
+                                                   double* __restrict__ aux, uint32_t* __restrict__ words,
+                                                   int* __restrict__ counters) {
+    const DescHeader* H = hdr(desc);
+    if (counters && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;
+    const int s = blockIdx.y;
+    if (s >= H->n_src) return;
+    const SrcDesc* S = srcs(desc) + s;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S->n_img) return;
+    const RoomDesc* R = rooms(desc) + S->room;
+    const int64_t row = S->img_off + i;
+    double* out = table + 4 * row;
+    if (i == 0) {   // direct path: the source itself, no reflection (Sec. III-D)
+        out[0] = S->pos[0];
+        out[1] = S->pos[1];
+        out[2] = S->pos[2];
+        out[3] = 0.0;
+        if (aux) {
+            for (int k = 0; k < 8; ++k) aux[8 * row + k] = 0.0;
+            aux[8 * row + 4] = 1.0;
+            aux[8 * row + 5] = S->d0;
+        }
+        if (words)
+            for (int k = 0; k < 4; ++k) words[4 * row + k] = 0u;
+        return;
+    }
+    uint32_t x[4] = {static_cast<uint32_t>(i - 1), static_cast<uint32_t>(S->s_local), 0u, 0u};
+    philox4x32_10(x, S->key0, S->key1);
+    const double two_m32 = 2.3283064365386963e-10;   // 2^-32
+    const double u0 = (static_cast<double>(x[0]) + 0.5) * two_m32;
+    const double u1 = (static_cast<double>(x[1]) + 0.5) * two_m32;
+    const double u2 = (static_cast<double>(x[2]) + 0.5) * two_m32;
+    const double u3 = (static_cast<double>(x[3]) + 0.5) * two_m32;
+    const double theta = u0 * kTwoPi;                          // azimuth ~ U[0, 2 pi]
+    const double phi = (u1 - 0.5) * kPi;                       // elevation ~ U[-pi/2, pi/2]
+    const double arg = H->a3 + u2 * (H->b3 - H->a3);           // inverse CDF of Eq. 3
+    const double xhat = cbrt_rn(arg);
+    const double p = H->a + u3 * H->b_minus_a;                 // p ~ U(a, b)
+    const double tt = (xhat - H->alpha) / H->beta_minus_alpha;
+    const double dr = 1.0 + tt * (S->q - 1.0);                 // Eq. 4
+    const double dist = S->d0 * dr;                            // D = d0 DR
+    const double s2 = dist / S->ct;
+    double g = 1.0 + (s2 * s2) * (S->rrmax - 1.0);             // Eq. 6
+    double drt;
+    if (H->tau_code == kTauQuarter) drt = sqrt_rn(sqrt_rn(dr));
+    else if (H->tau_code == kTauHalf) drt = sqrt_rn(dr);
+    else drt = dr;
+    g = g + p * drt;
+    g = fmin(fmax(g, 1.0), S->rrmax);
+    double st, ctheta, sp, cp;
+    sincos(theta, &st, &ctheta);
+    sincos(phi, &sp, &cp);
+    out[0] = R->centre[0] + dist * (cp * ctheta);
+    out[1] = R->centre[1] + dist * (cp * st);
+    out[2] = R->centre[2] + dist * sp;
+    out[3] = g;
+    if (aux) {
+        double* a = aux + 8 * row;
+        a[0] = theta;
+        a[1] = phi;
+        a[2] = xhat;
+        a[3] = p;
+        a[4] = dr;
+        a[5] = dist;
+        a[6] = g;
+        a[7] = 0.0;
+    }
+    if (words)
+        for (int k = 0; k < 4; ++k) words[4 * row + k] = x[k];
+}
+
+// ---------------------------------------------------------------------------
+// Per-pair setup shared by the render and the adjoint
+// ---------------------------------------------------------------------------
+struct Pair {
+    int k;        // tap centre floor(t + 1/2)
+    float dl;     // fractional delay t - k in [-1/2, 1/2]
+    float A;      // r^g / D
+    float S;      // A sin(pi dl) / pi
+    float cy, sy; // cos, sin of pi dl / 81
+    float sinc;   // sin(pi dl) / (pi dl), 1 at 0
+    float ux, uy, uz, D;
+};
+
+__device__ __forceinline__ Pair pair_setup(double px, double py, double pz, double mx, double my, double mz,
+                                           double fs_over_c, float amp) {
+    Pair P;
+    const double dx = px - mx, dy = py - my, dz = pz - mz;
+    const double d2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+    const double D = __builtin_sqrt(d2);
+    const double t = D * fs_over_c;
+    const double kf = __builtin_floor(t + 0.5);
+    P.k = static_cast<int>(kf);
+    P.dl = static_cast<float>(t - kf);
+    const float Df = static_cast<float>(D);
+    const float invD = 1.0f / Df;
+    P.A = amp * invD;
+    P.D = Df;
+    const double invDd = 1.0 / D;
+    P.ux = static_cast<float>(dx * invDd);
+    P.uy = static_cast<float>(dy * invDd);
+    P.uz = static_cast<float>(dz * invDd);
+    const float sp = sinpif(P.dl);
+    P.S = P.A * sp * kInvPiF;
+    const float y = (kPiF / 81.0f) * P.dl;
+    const float y2 = y * y;
+    // |y| <= pi / 162: three Taylor terms are exact to FP32 rounding
+    P.cy = __builtin_fmaf(y2, __builtin_fmaf(y2, 1.0f / 24.0f, -0.5f), 1.0f);
+    P.sy = y * __builtin_fmaf(y2, __builtin_fmaf(y2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+    P.sinc = (P.dl == 0.0f) ? 1.0f : sp / (kPiF * P.dl);
+    return P;
+}
+
+// ---- forward taps.  With m = j - 40, x = m - dl and S = A sin(pi dl)/pi:
+//   A P(x) = (-1)^(m+1) S cos^2(pi x / 81) / x.
+// cos(pi x/81) = cos(pi m/81) cos(pi dl/81) + sin(pi m/81) sin(pi dl/81).
+// sqrt(|S|) is folded into the two per-pair factors and sign(S) (-1)^(m+1)
+// into the divisor, so a tap costs one FMA for the divisor, one rcp, two for
+// the window and two multiplies.
+template <int J>
+__device__ __forceinline__ void fwd_tap(float* __restrict__ row, float cd, float sd, float sig, float sdl, float v0) {
+    constexpr int m = J - kHalf;
+    if constexpr (m == 0) {
+        atomicAdd(row + J, v0);
+    } else {
+        constexpr float M = static_cast<float>(m);
+        constexpr float C = static_cast<float>(ct_cos(kPiOver81 * m));
+        constexpr float Sn = static_cast<float>(ct_sin(kPiOver81 * m));
+        const float x = (m & 1) ? __builtin_fmaf(sig, M, -sdl) : __builtin_fmaf(-sig, M, sdl);
+        const float rx = __builtin_amdgcn_rcpf(x);
+        const float c = __builtin_fmaf(C, cd, Sn * sd);
+        atomicAdd(row + J, (c * c) * rx);
+    }
+}
+
+template <int... J>
+__device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, float* __restrict__ row, float cd,
+                                         float sd, float sig, float sdl, float v0) {
+    (fwd_tap<J>(row, cd, sd, sig, sdl, v0), ...);
+}
+
+// ---- backward taps: s0 += G A P(x), s1 += G A P'(x) with
+//   A P'(x) = (1/x) [(-1)^m (A cos(pi dl) w + (2 pi/81) S sw cw) - A P(x)],
+//   w = cw^2, cw = cos(pi x/81), sw = sin(pi x/81).
+template <int J>
+__device__ __forceinline__ void bwd_tap(const float* __restrict__ row, float cy, float sy, float dl, float S,
+                                        float Ac, float S2, float v0, float dp0, float& s0, float& s1) {
+    constexpr int m = J - kHalf;
+    const float G = row[J];
+    if constexpr (m == 0) {
+        s0 = __builtin_fmaf(G, v0, s0);
+        s1 = __builtin_fmaf(G, dp0, s1);
+    } else {
+        constexpr float M = static_cast<float>(m);
+        constexpr float C = static_cast<float>(ct_cos(kPiOver81 * m));
+        constexpr float Sn = static_cast<float>(ct_sin(kPiOver81 * m));
+        constexpr float sgn = (m & 1) ? -1.0f : 1.0f;   // (-1)^m
+        const float rx = __builtin_amdgcn_rcpf(M - dl);
+        const float cw = __builtin_fmaf(C, cy, Sn * sy);
+        const float sw = __builtin_fmaf(Sn, cy, -(C * sy));
+        const float w = cw * cw;
+        const float val = (-sgn * S) * w * rx;
+        const float inner = __builtin_fmaf(Ac, w, S2 * (sw * cw));
+        const float dp = rx * __builtin_fmaf(sgn, inner, -val);
+        s0 = __builtin_fmaf(G, val, s0);
+        s1 = __builtin_fmaf(G, dp, s1);
+    }
+}
+
+template <int... J>
+__device__ __forceinline__ void bwd_taps(std::integer_sequence<int, J...>, const float* __restrict__ row, float cy,
+                                         float sy, float dl, float S, float Ac, float S2, float v0, float dp0,
+                                         float& s0, float& s1) {
+    (bwd_tap<J>(row, cy, sy, dl, S, Ac, S2, v0, dp0, s0, s1), ...);
+}
+
+// sinc'(x) for |x| <= 1/2 from its Taylor series (no cancellation near 0):
+//   sinc'(x) = sum_{k>=1} (-1)^k 2k pi^(2k) x^(2k-1) / (2k+1)!
+__device__ __forceinline__ float dsinc_small(float x) {
+    const float z = kPiF * kPiF * x * x;
+    // coefficients (-1)^k 2k / (2k+1)! for k = 1..8, Horner in z
+    float acc = 16.0f / 355687428096000.0f;
+    acc = __builtin_fmaf(acc, z, -14.0f / 1307674368000.0f);
+    acc = __builtin_fmaf(acc, z, 12.0f / 6227020800.0f);
+    acc = __builtin_fmaf(acc, z, -10.0f / 39916800.0f);
+    acc = __builtin_fmaf(acc, z, 8.0f / 362880.0f);
+    acc = __builtin_fmaf(acc, z, -6.0f / 5040.0f);
+    acc = __builtin_fmaf(acc, z, 4.0f / 120.0f);
+    acc = __builtin_fmaf(acc, z, -2.0f / 6.0f);
+    return acc * (kPiF * kPiF * x);
+}
+
+struct ItemCtx {
+    WorkItem w;
+    int room, s_local, T, n_mic_room, mic0_glob, n_img, rowlen;
+    int64_t out_off, img_off;
+    double fs_over_c, cx, cy, cz;
+    double r, log2r;
+    float margin;   // max |mic - centre| fs / c + 2 samples, for the tile test
+};
+
+__device__ __forceinline__ void load_item(const void* desc, int item, const double* __restrict__ mic,
+                                          const double* __restrict__ r_in, ItemCtx& c) {
+    c.w = items(desc)[item];
+    const SrcDesc* S = srcs(desc) + c.w.src;
+    const RoomDesc* R = rooms(desc) + S->room;
+    c.room = S->room;
+    c.s_local = S->s_local;
+    c.T = R->T;
+    c.n_mic_room = R->n_mic;
+    c.mic0_glob = R->mic0 + c.w.mic0;
+    c.n_img = S->n_img;
+    c.img_off = S->img_off;
+    c.out_off = R->out_off;
+    c.fs_over_c = R->fs_over_c;
+    c.cx = R->centre[0];
+    c.cy = R->centre[1];
+    c.cz = R->centre[2];
+    c.r = r_in ? r_in[S->room] : R->r;
+    c.log2r = log2(c.r);
+    c.rowlen = c.w.len + 2 * kHalo;
+    double mx = 0.0;
+    for (int m = 0; m < c.w.n_mic; ++m) {
+        const double* q = mic + 3 * (c.mic0_glob + m);
+        const double ex = q[0] - c.cx, ey = q[1] - c.cy, ez = q[2] - c.cz;
+        mx = fmax(mx, __builtin_sqrt(ex * ex + ey * ey + ez * ez));
+    }
+    c.margin = static_cast<float>(mx * c.fs_over_c) + 2.0f;
+}
+
+// Image position / reflection count of table row i (row 0 follows src).
+__device__ __forceinline__ void image_row(const ItemCtx& c, int i, const double* __restrict__ table,
+                                          const double* __restrict__ src, int src_glob, double& px, double& py,
+                                          double& pz, double& g) {
+    if (i == 0) {
+        px = src[3 * src_glob + 0];
+        py = src[3 * src_glob + 1];
+        pz = src[3 * src_glob + 2];
+        g = 0.0;
+    } else {
+        const double4 v = *reinterpret_cast<const double4*>(table + 4 * (c.img_off + i));
+        px = v.x;
+        py = v.y;
+        pz = v.z;
+        g = v.w;
+    }
+}
+
+// Deterministic compaction of the rows [seg0, seg1) whose pulses may reach
+// the tile core into list[]; returns the count.  Order: row index.
+template <int NT>
+__device__ int compact_rows(const ItemCtx& c, int seg0, int seg1, const double* __restrict__ table,
+                            const double* __restrict__ src, int* __restrict__ list, int* __restrict__ wave_cnt) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = NT / 64;
+    int total = 0;
+    const float lo = static_cast<float>(c.w.t0) - c.margin - 41.0f;
+    const float hi = static_cast<float>(c.w.t0 + c.w.len) + c.margin + 41.0f;
+    for (int base = seg0; base < seg1; base += NT) {
+        const int i = base + tid;
+        bool keep = false;
+        if (i < seg1) {
+            double px, py, pz, g;
+            image_row(c, i, table, src, c.w.src, px, py, pz, g);
+            const float ex = static_cast<float>(px - c.cx), ey = static_cast<float>(py - c.cy),
+                        ez = static_cast<float>(pz - c.cz);
+            const float tc = __builtin_sqrtf(ex * ex + ey * ey + ez * ez) * static_cast<float>(c.fs_over_c);
+            keep = tc >= lo && tc < hi;
+        }
+        const uint64_t mask = __ballot(keep);
+        const int before = __popcll(mask & ((uint64_t(1) << lane) - 1));
+        if (lane == 0) wave_cnt[wave] = __popcll(mask);
+        __syncthreads();
+        int off = total;
+        for (int k = 0; k < wave; ++k) off += wave_cnt[k];
+        int sum = 0;
+        for (int k = 0; k < NW; ++k) sum += wave_cnt[k];
+        if (keep) list[off + before] = i;
+        total += sum;
+        __syncthreads();
+    }
+    return total;
+}
+
+// ---------------------------------------------------------------------------
+// Render
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ desc, const double* __restrict__ table,
+                                                     const double* __restrict__ mic, const double* __restrict__ src,
+                                                     const double* __restrict__ r_in, float* __restrict__ out,
+                                                     int* __restrict__ counters) {
+    extern __shared__ float acc[];
+    __shared__ int list[kListCap];
+    __shared__ int wave_cnt[NT / 64];
+    __shared__ int s_item;
+    const DescHeader* H = hdr(desc);
+    const int n_items = H->n_items;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counters[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= n_items) break;
+        ItemCtx c;
+        load_item(desc, item, mic, r_in, c);
+        const int mg = c.w.n_mic;
+        const int nacc = mg * c.rowlen;
+        for (int k = tid; k < nacc; k += NT) acc[k] = 0.0f;
+        // this thread's microphone and image slot
+        const int ipp = NT / mg;
+        const int my_m = tid % mg, my_slot = tid / mg;
+        const double* mq = mic + 3 * (c.mic0_glob + my_m);
+        const double mx = mq[0], my = mq[1], mz = mq[2];
+        float* row = acc + my_m * c.rowlen;
+        const int shift = kHalo - kHalf - c.w.t0;   // LDS index of tap 0 = k + shift
+        __syncthreads();
+        for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
+            const int seg1 = min(c.n_img, seg0 + kListCap);
+            int n_list = seg1 - seg0;
+            if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
+            if (my_slot < ipp) {
+                for (int e = my_slot; e < n_list; e += ipp) {
+                    const int i = c.w.full ? seg0 + e : list[e];
+                    double px, py, pz, g;
+                    image_row(c, i, table, src, c.w.src, px, py, pz, g);
+                    const float amp = exp2f(static_cast<float>(g * c.log2r));
+                    const Pair P = pair_setup(px, py, pz, mx, my, mz, c.fs_over_c, amp);
+                    const int b0 = P.k + shift;
+                    if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
+                    const float aS = fabsf(P.S);
+                    const float sq = __builtin_sqrtf(aS);
+                    const float cd = sq * P.cy, sd = sq * P.sy;
+                    const float sig = P.S < 0.0f ? -1.0f : 1.0f;
+                    const float sdl = sig * P.dl;
+                    const float v0 = P.A * P.sinc * (P.cy * P.cy);
+                    fwd_taps(std::make_integer_sequence<int, kTaps>{}, row + b0, cd, sd, sig, sdl, v0);
+                }
+            }
+            __syncthreads();
+        }
+        // writeback of the tile core, samples [t0, min(t0 + len, T))
+        const int nvalid = min(c.w.len, c.T - c.w.t0);
+        for (int m = 0; m < mg; ++m) {
+            float* dst = out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + m) * c.T +
+                         c.w.t0;
+            const float* srcrow = acc + m * c.rowlen + kHalo;
+            for (int n = tid; n < nvalid; n += NT) dst[n] = srcrow[n];
+        }
+        __syncthreads();
+    }
+    // the last workgroup to finish rewinds the queue for the next launch
+    if (tid == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counters[1], 1);
+        if (done == static_cast<int>(gridDim.x) - 1) {
+            atomicExch(&counters[0], 0);
+            atomicExch(&counters[1], 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ void __launch_bounds__(NT) backward_kernel(const void* __restrict__ desc,
+                                                       const double* __restrict__ table,
+                                                       const double* __restrict__ mic,
+                                                       const double* __restrict__ src,
+                                                       const double* __restrict__ r_in,
+                                                       const float* __restrict__ gout,
+                                                       float* __restrict__ partials, int* __restrict__ counters) {
+    extern __shared__ float tile[];
+    __shared__ int list[kListCap];
+    __shared__ int wave_cnt[NT / 64];
+    __shared__ int s_item;
+    const DescHeader* H = hdr(desc);
+    const int n_items = H->n_items;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counters[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= n_items) break;
+        ItemCtx c;
+        load_item(desc, item, mic, r_in, c);
+        const int mg = c.w.n_mic;
+        // dL/dh of the tile core; zero in the halo and beyond T, so that each
+        // pair counts only the taps of this tile
+        for (int m = 0; m < mg; ++m) {
+            const float* g = gout + c.out_off +
+                             (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + m) * c.T;
+            for (int k = tid; k < c.rowlen; k += NT) {
+                const int n = c.w.t0 - kHalo + k;
+                const bool core = k >= kHalo && k < kHalo + c.w.len && n < c.T;
+                tile[m * c.rowlen + k] = core ? g[n] : 0.0f;
+            }
+        }
+        const int ipp = NT / mg;
+        const int my_m = tid % mg, my_slot = tid / mg;
+        const double* mq = mic + 3 * (c.mic0_glob + my_m);
+        const double mx = mq[0], my = mq[1], mz = mq[2];
+        const float* row = tile + my_m * c.rowlen;
+        const int shift = kHalo - kHalf - c.w.t0;
+        const float fsc = static_cast<float>(c.fs_over_c);
+        const float inv_r = static_cast<float>(1.0 / c.r);
+        float gmx = 0.f, gmy = 0.f, gmz = 0.f, gsx = 0.f, gsy = 0.f, gsz = 0.f, gr = 0.f;
+        __syncthreads();
+        for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
+            const int seg1 = min(c.n_img, seg0 + kListCap);
+            int n_list = seg1 - seg0;
+            if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
+            if (my_slot < ipp) {
+                for (int e = my_slot; e < n_list; e += ipp) {
+                    const int i = c.w.full ? seg0 + e : list[e];
+                    double px, py, pz, g;
+                    image_row(c, i, table, src, c.w.src, px, py, pz, g);
+                    const float amp = exp2f(static_cast<float>(g * c.log2r));
+                    const Pair P = pair_setup(px, py, pz, mx, my, mz, c.fs_over_c, amp);
+                    const int b0 = P.k + shift;
+                    if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
+                    const float cpd = cospif(P.dl);
+                    const float Ac = P.A * cpd;
+                    const float S2 = (2.0f * kPiF / 81.0f) * P.S;
+                    const float v0 = P.A * P.sinc * (P.cy * P.cy);
+                    // A P'(-dl): sinc'(-dl) w + sinc(dl) w'(-dl), w'(-dl) = (2 pi/81) sy cy
+                    const float dp0 = P.A * (-dsinc_small(P.dl) * (P.cy * P.cy) +
+                                             P.sinc * (2.0f * kPiF / 81.0f) * P.sy * P.cy);
+                    float s0 = 0.f, s1 = 0.f;
+                    bwd_taps(std::make_integer_sequence<int, kTaps>{}, row + b0, P.cy, P.sy, P.dl, P.S, Ac, S2, v0,
+                             dp0, s0, s1);
+                    const float q = __builtin_fmaf(fsc, s1, s0 / P.D);
+                    gmx = __builtin_fmaf(P.ux, q, gmx);
+                    gmy = __builtin_fmaf(P.uy, q, gmy);
+                    gmz = __builtin_fmaf(P.uz, q, gmz);
+                    if (i == 0) {
+                        gsx -= P.ux * q;
+                        gsy -= P.uy * q;
+                        gsz -= P.uz * q;
+                    }
+                    gr = __builtin_fmaf(static_cast<float>(g) * inv_r, s0, gr);
+                }
+            }
+            __syncthreads();
+        }
+        // fixed-order reduction over the threads of each microphone
+        float* red = tile;   // reuse: NT x 7 floats
+        red[tid * 7 + 0] = gmx;
+        red[tid * 7 + 1] = gmy;
+        red[tid * 7 + 2] = gmz;
+        red[tid * 7 + 3] = gsx;
+        red[tid * 7 + 4] = gsy;
+        red[tid * 7 + 5] = gsz;
+        red[tid * 7 + 6] = gr;
+        __syncthreads();
+        float* part = partials + static_cast<int64_t>(item) * kPartialStride;
+        if (tid < mg * 3) {
+            const int m = tid / 3, k = tid % 3;
+            float sum = 0.f;
+            for (int t = m; t < ipp * mg; t += mg) sum += red[t * 7 + k];
+            part[m * 3 + k] = sum;
+        } else if (tid >= 64 && tid < 68) {
+            const int k = tid - 64;   // 0..2 source, 3 r
+            float sum = 0.f;
+            for (int t = 0; t < ipp * mg; ++t) sum += red[t * 7 + 3 + k];
+            part[3 * kMaxMicGroup + k] = sum;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counters[1], 1);
+        if (done == static_cast<int>(gridDim.x) - 1) {
+            atomicExch(&counters[0], 0);
+            atomicExch(&counters[1], 0);
+        }
+    }
+}
+
+// One workgroup per room: sums the partials of the room's items in the
+// plan's fixed order.
+__global__ void __launch_bounds__(256) finalize_kernel(const void* __restrict__ desc,
+                                                        const float* __restrict__ partials,
+                                                        float* __restrict__ grad_mic, float* __restrict__ grad_src,
+                                                        float* __restrict__ grad_r) {
+    const int b = blockIdx.x;
+    const DescHeader* H = hdr(desc);
+    if (b >= H->n_rooms) return;
+    const RoomDesc* R = rooms(desc) + b;
+    const int32_t* ri = room_items(desc) + R->item0;
+    const WorkItem* it = items(desc);
+    const int n_out = 3 * R->n_mic + 3 * R->n_src + 1;
+    for (int o = threadIdx.x; o < n_out; o += blockDim.x) {
+        float sum = 0.f;
+        if (o < 3 * R->n_mic) {
+            const int m = o / 3, k = o % 3;
+            for (int j = 0; j < R->n_item; ++j) {
+                const WorkItem& w = it[ri[j]];
+                if (m >= w.mic0 && m < w.mic0 + w.n_mic)
+                    sum += partials[static_cast<int64_t>(ri[j]) * kPartialStride + (m - w.mic0) * 3 + k];
+            }
+            if (grad_mic) grad_mic[3 * (R->mic0 + m) + k] = sum;
+        } else if (o < 3 * R->n_mic + 3 * R->n_src) {
+            const int s = (o - 3 * R->n_mic) / 3, k = (o - 3 * R->n_mic) % 3;
+            for (int j = 0; j < R->n_item; ++j) {
+                const WorkItem& w = it[ri[j]];
+                if (w.src == R->src0 + s)
+                    sum += partials[static_cast<int64_t>(ri[j]) * kPartialStride + 3 * kMaxMicGroup + k];
+            }
+            if (grad_src) grad_src[3 * (R->src0 + s) + k] = sum;
+        } else {
+            for (int j = 0; j < R->n_item; ++j)
+                sum += partials[static_cast<int64_t>(ri[j]) * kPartialStride + 3 * kMaxMicGroup + 3];
+            if (grad_r) grad_r[b] = sum;
+        }
+    }
+}
+
+__global__ void zero_counters_kernel(int* counters) {
+    if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+}
+
+__global__ void philox_kernel(const uint32_t* __restrict__ ctr, const uint32_t* __restrict__ key,
+                              uint32_t* __restrict__ out, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t x[4] = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+    philox4x32_10(x, key[2 * i], key[2 * i + 1]);
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = x[k];
+}
+
+__global__ void cbrt_kernel(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = x[i];
+    // positive normal arguments only (the draws never produce others)
+    y[i] = (v >= 2.2250738585072014e-308 && v < __builtin_inf()) ? cbrt_rn(v)
+                                                                   : (v == 0.0 ? 0.0 : __builtin_nan(""));
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+int check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fr_fail(FRAMRIR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return FRAMRIR_OK;
+}
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int framrir_draw(const framrir_plan* plan, const void* desc_dev, double* table_dev, double* aux_dev,
+                            uint32_t* words_dev, void* stream) {
+    if (!plan || !desc_dev || !table_dev) return fr_fail(FRAMRIR_E_INVALID_ARG, "plan, desc and table required");
+    if (!aligned(desc_dev, 256) || !aligned(table_dev, 32))
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "desc must be 256-byte and table 32-byte aligned");
+    const DescHeader& H = plan->header;
+    const dim3 grid((H.max_img + 255) / 256, H.n_src);
+    hipLaunchKernelGGL(draw_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), desc_dev, table_dev,
+                       aux_dev, words_dev, static_cast<int*>(nullptr));
+    return check_launch("draw_kernel");
+}
+
+namespace {
+
+template <typename F>
+int allow_lds(F kernel, int bytes) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return fr_fail(FRAMRIR_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+    return FRAMRIR_OK;
+}
+
+int launch_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev, const double* mic_dev,
+                  const double* src_dev, const double* r_dev, float* out_dev, int* counters, hipStream_t st) {
+    const int lds = plan->launch.lds_bytes;
+    const dim3 grid(plan->grid), block(plan->launch.wg_threads);
+    switch (plan->launch.wg_threads) {
+#define FR_CASE(NT)                                                                                         \
+    case NT:                                                                                                \
+        if (int rc = allow_lds(render_kernel<NT>, lds)) return rc;                                          \
+        hipLaunchKernelGGL(render_kernel<NT>, grid, block, lds, st, desc_dev, table_dev, mic_dev, src_dev, \
+                           r_dev, out_dev, counters);                                                       \
+        break;
+        FR_CASE(256)
+        FR_CASE(512)
+        FR_CASE(1024)
+#undef FR_CASE
+        default:
+            return fr_fail(FRAMRIR_E_UNSUPPORTED, "wg_threads %d not compiled (256, 512, 1024)",
+                           plan->launch.wg_threads);
+    }
+    return check_launch("render_kernel");
+}
+
+int check_render_args(const framrir_plan* plan, const void* desc_dev, const double* table_dev, const double* mic_dev,
+                      const double* src_dev, const void* out_dev, void* ws_dev, size_t ws_bytes, int64_t need) {
+    if (!plan || !desc_dev || !table_dev || !mic_dev || !src_dev || !out_dev || !ws_dev)
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
+    if (!aligned(desc_dev, 256) || !aligned(table_dev, 32) || !aligned(ws_dev, 256) || !aligned(out_dev, 16))
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned buffer");
+    if (static_cast<int64_t>(ws_bytes) < need)
+        return fr_fail(FRAMRIR_E_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, static_cast<long long>(need));
+    return FRAMRIR_OK;
+}
+
+}  // namespace
+
+extern "C" int framrir_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                              const double* mic_dev, const double* src_dev, const double* r_dev, float* out_dev,
+                              void* ws_dev, size_t ws_bytes, void* stream) {
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_bytes : 0);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int* counters = static_cast<int*>(ws_dev);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, counters);
+    if ((rc = check_launch("zero_counters_kernel"))) return rc;
+    return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, counters, st);
+}
+
+extern "C" int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                               const double* mic_dev, const double* src_dev, const double* r_dev, float* out_dev,
+                               void* ws_dev, size_t ws_bytes, void* stream) {
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_bytes : 0);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int* counters = static_cast<int*>(ws_dev);
+    const DescHeader& H = plan->header;
+    const dim3 grid((H.max_img + 255) / 256, H.n_src);
+    hipLaunchKernelGGL(draw_kernel, grid, dim3(256), 0, st, desc_dev, table_dev, static_cast<double*>(nullptr),
+                       static_cast<uint32_t*>(nullptr), counters);
+    if ((rc = check_launch("draw_kernel"))) return rc;
+    return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, counters, st);
+}
+
+extern "C" int framrir_render_backward(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                                       const double* mic_dev, const double* src_dev, const double* r_dev,
+                                       const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
+                                       float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, grad_out_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_bwd_bytes : 0);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int* counters = static_cast<int*>(ws_dev);
+    float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + kWsCounterBytes);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, counters);
+    if ((rc = check_launch("zero_counters_kernel"))) return rc;
+    const int lds = plan->launch.lds_bytes;
+    const dim3 grid(plan->grid), block(plan->launch.wg_threads);
+    switch (plan->launch.wg_threads) {
+#define FR_CASE(NT)                                                                                           \
+    case NT:                                                                                                  \
+        if (int rc2 = allow_lds(backward_kernel<NT>, lds)) return rc2;                                        \
+        hipLaunchKernelGGL(backward_kernel<NT>, grid, block, lds, st, desc_dev, table_dev, mic_dev, src_dev, \
+                           r_dev, grad_out_dev, partials, counters);                                          \
+        break;
+        FR_CASE(256)
+        FR_CASE(512)
+        FR_CASE(1024)
+#undef FR_CASE
+        default:
+            return fr_fail(FRAMRIR_E_UNSUPPORTED, "wg_threads %d not compiled", plan->launch.wg_threads);
+    }
+    if ((rc = check_launch("backward_kernel"))) return rc;
+    hipLaunchKernelGGL(finalize_kernel, dim3(plan->header.n_rooms), dim3(256), 0, st, desc_dev, partials,
+                       grad_mic_dev, grad_src_dev, grad_r_dev);
+    return check_launch("finalize_kernel");
+}
+
+extern "C" int framrir_philox4x32(const uint32_t* ctr_dev, const uint32_t* key_dev, uint32_t* out_dev, int64_t n,
+                                  void* stream) {
+    if (!ctr_dev || !key_dev || !out_dev || n < 0) return fr_fail(FRAMRIR_E_INVALID_ARG, "bad philox arguments");
+    if (n == 0) return FRAMRIR_OK;
+    hipLaunchKernelGGL(philox_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), ctr_dev, key_dev, out_dev, n);
+    return check_launch("philox_kernel");
+}
+
+extern "C" int framrir_cbrt_rn(const double* x_dev, double* y_dev, int64_t n, void* stream) {
+    if (!x_dev || !y_dev || n < 0) return fr_fail(FRAMRIR_E_INVALID_ARG, "bad cbrt arguments");
+    if (n == 0) return FRAMRIR_OK;
+    hipLaunchKernelGGL(cbrt_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), x_dev, y_dev, n);
+    return check_launch("cbrt_kernel");
+}

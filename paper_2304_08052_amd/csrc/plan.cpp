@@ -1,0 +1,455 @@
+// Host planner of the FRAM-RIR library: validation, per-room and per-source
+// scalars (Sec. II, III-A, III-C; Eq. 2, Eq. 5), image counts, the device
+// descriptor blob and the render work items.  No device calls here.
+//
+// Build with -ffp-contract=off: every FP64 expression below is rounded one
+// operation at a time in the order written, so the scalars that feed the
+// bit-exact draws are a function of the inputs and the C library alone.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/framrir.h"
+#include "framrir_internal.h"
+#include "plan_internal.h"
+
+using namespace framrir;
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+int fr_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = std::string(framrir_strerror(code)) + ": " + buf;
+    return code;
+}
+
+extern "C" int framrir_last_error_detail(char* buf, size_t n) {
+    if (buf && n > 0) {
+        const size_t k = std::min(n - 1, g_last_error.size());
+        std::memcpy(buf, g_last_error.data(), k);
+        buf[k] = '\0';
+    }
+    return static_cast<int>(g_last_error.size());
+}
+
+extern "C" const char* framrir_strerror(int code) {
+    switch (code) {
+        case FRAMRIR_OK: return "ok";
+        case FRAMRIR_E_INVALID_ARG: return "invalid argument";
+        case FRAMRIR_E_GEOMETRY: return "invalid geometry";
+        case FRAMRIR_E_RANGE: return "value out of range";
+        case FRAMRIR_E_WORKSPACE: return "workspace too small";
+        case FRAMRIR_E_DEVICE: return "device error";
+        case FRAMRIR_E_UNSUPPORTED: return "unsupported";
+        default: return "unknown error";
+    }
+}
+
+extern "C" int framrir_version(void) { return (1 << 16) | 0; }
+
+// ---------------------------------------------------------------------------
+// Scalars
+// ---------------------------------------------------------------------------
+namespace {
+
+bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+bool strictly_inside(const double* p, const double* size) {
+    for (int k = 0; k < 3; ++k)
+        if (!(p[k] > 0.0 && p[k] < size[k])) return false;
+    return true;
+}
+
+// R = V / S of the empty shoebox (Sec. III-A); r from Eq. 2 as printed.
+double eyring_r(const double* size, double rt60) {
+    const double lx = size[0], ly = size[1], lz = size[2];
+    const double volume = (lx * ly) * lz;
+    const double area = 2.0 * ((lx * ly + lx * lz) + ly * lz);
+    const double big_r = volume / area;
+    const double x = (0.16 * big_r) / rt60;
+    const double eps = 1.0 - std::exp(-x);
+    return std::sqrt(1.0 - eps * eps);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms, const framrir_params* prm_in,
+                                   const framrir_launch* launch_in, const double* src, const double* mic,
+                                   framrir_plan** out) {
+    if (!out) return fr_fail(FRAMRIR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!rooms_in || !src || !mic) return fr_fail(FRAMRIR_E_INVALID_ARG, "rooms, src and mic must be non-NULL");
+    if (n_rooms <= 0) return fr_fail(FRAMRIR_E_INVALID_ARG, "n_rooms = %d must be >= 1", n_rooms);
+
+    framrir_params prm;
+    if (prm_in) {
+        prm = *prm_in;
+    } else {
+        prm = framrir_params{0.25, 1.0, -2.0, 2.0, 0.25, 1024, 4096, FRAMRIR_TAPS, 0u};
+    }
+    framrir_launch launch = launch_in ? *launch_in : framrir_launch{131072, 1024, 0, 8};
+    if (launch.max_mic_group == 0) launch.max_mic_group = 8;
+
+    // ---- method parameters
+    if (!(std::isfinite(prm.alpha) && std::isfinite(prm.beta) && std::isfinite(prm.a) && std::isfinite(prm.b) &&
+          std::isfinite(prm.tau)))
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "non-finite method parameter");
+    if (!(prm.alpha >= 0.0 && prm.alpha < prm.beta && prm.beta <= 1.0))
+        return fr_fail(FRAMRIR_E_RANGE, "need 0 <= alpha < beta <= 1 (alpha=%g beta=%g)", prm.alpha, prm.beta);
+    if (!(prm.a <= prm.b)) return fr_fail(FRAMRIR_E_RANGE, "need a <= b (a=%g b=%g)", prm.a, prm.b);
+    int32_t tau_code;
+    if (prm.tau == 0.25) tau_code = kTauQuarter;
+    else if (prm.tau == 0.5) tau_code = kTauHalf;
+    else if (prm.tau == 1.0) tau_code = kTauOne;
+    else return fr_fail(FRAMRIR_E_RANGE, "tau must be 0.25, 0.5 or 1 (got %g)", prm.tau);
+    if (!(prm.img_lo >= 0 && prm.img_lo <= prm.img_hi && prm.img_hi <= 65535))
+        return fr_fail(FRAMRIR_E_RANGE, "need 0 <= img_lo <= img_hi <= 65535 (%d, %d)", prm.img_lo, prm.img_hi);
+    if (prm.taps != FRAMRIR_TAPS) return fr_fail(FRAMRIR_E_UNSUPPORTED, "taps must be 81 (got %d)", prm.taps);
+    if (prm.flags != 0u) return fr_fail(FRAMRIR_E_UNSUPPORTED, "flags must be 0");
+
+    // ---- launch shape
+    if (launch.wg_threads < 64 || launch.wg_threads > 1024 || launch.wg_threads % 64 != 0)
+        return fr_fail(FRAMRIR_E_RANGE, "wg_threads must be a multiple of 64 in [64, 1024] (got %d)",
+                       launch.wg_threads);
+    if (launch.lds_bytes < 4096 || launch.lds_bytes > kMaxAccLdsBytes)
+        return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be in [4096, %d] (got %d)", kMaxAccLdsBytes,
+                       launch.lds_bytes);
+    if (launch.lds_bytes < 28 * launch.wg_threads)
+        return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be >= 28 * wg_threads (backward reduction)");
+    if (launch.max_mic_group < 1 || launch.max_mic_group > kMaxMicGroup)
+        return fr_fail(FRAMRIR_E_RANGE, "max_mic_group must be in [1, %d]", kMaxMicGroup);
+    if (launch.grid_wgs < 0) return fr_fail(FRAMRIR_E_RANGE, "grid_wgs must be >= 0");
+
+    framrir_plan* plan = new (std::nothrow) framrir_plan();
+    if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "out of host memory");
+    plan->launch = launch;
+    plan->prm = prm;
+
+    std::vector<RoomDesc>& rd = plan->rooms;
+    std::vector<SrcDesc>& sd = plan->srcs;
+    rd.resize(n_rooms);
+    int64_t out_off = 0, img_off = 0;
+    int32_t src_row = 0, mic_row = 0, max_img = 0, max_T = 0;
+
+    for (int32_t b = 0; b < n_rooms; ++b) {
+        const framrir_room& rm = rooms_in[b];
+        if (!finite3(rm.size) || !std::isfinite(rm.rt60) || !std::isfinite(rm.fs) || !std::isfinite(rm.c)) {
+            delete plan;
+            return fr_fail(FRAMRIR_E_INVALID_ARG, "room %d: non-finite size, T60, fs or c", b);
+        }
+        if (!(rm.size[0] > 0.0 && rm.size[1] > 0.0 && rm.size[2] > 0.0)) {
+            delete plan;
+            return fr_fail(FRAMRIR_E_GEOMETRY, "room %d: dimensions must be > 0", b);
+        }
+        if (!(rm.rt60 > 0.0 && rm.fs > 0.0 && rm.c > 0.0)) {
+            delete plan;
+            return fr_fail(FRAMRIR_E_RANGE, "room %d: T60, fs and c must be > 0", b);
+        }
+        if (rm.n_src < 1 || rm.n_mic < 1 || rm.n_mic > FRAMRIR_MAX_MICS) {
+            delete plan;
+            return fr_fail(FRAMRIR_E_INVALID_ARG, "room %d: need n_src >= 1 and 1 <= n_mic <= %d", b,
+                           FRAMRIR_MAX_MICS);
+        }
+        const double t_samples = std::ceil(rm.rt60 * rm.fs);   // T = ceil(T60 fs)
+        if (!(t_samples >= 1.0 && t_samples <= 2147483647.0 - 256.0)) {
+            delete plan;
+            return fr_fail(FRAMRIR_E_RANGE, "room %d: T = ceil(T60 fs) out of range", b);
+        }
+        const int32_t T = static_cast<int32_t>(t_samples);
+        double r;
+        if (std::isnan(rm.r_override)) {
+            r = eyring_r(rm.size, rm.rt60);
+        } else {
+            r = rm.r_override;
+        }
+        if (!(r > 0.0 && r < 1.0)) {
+            delete plan;
+            return fr_fail(FRAMRIR_E_RANGE, "room %d: reflection coefficient r = %.17g not in (0, 1)", b, r);
+        }
+        // microphones: inside, and the centre in microphone order (Sec. III-B)
+        const double* mics = mic + 3 * static_cast<int64_t>(mic_row);
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+        for (int32_t m = 0; m < rm.n_mic; ++m) {
+            const double* p = mics + 3 * m;
+            if (!finite3(p)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_INVALID_ARG, "room %d mic %d: non-finite position", b, m);
+            }
+            if (!strictly_inside(p, rm.size)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_GEOMETRY, "room %d mic %d: not strictly inside the room", b, m);
+            }
+            cx += p[0];
+            cy += p[1];
+            cz += p[2];
+        }
+        const double nm = static_cast<double>(rm.n_mic);
+        RoomDesc& R = rd[b];
+        std::memset(&R, 0, sizeof(R));
+        R.fs_over_c = rm.fs / rm.c;
+        R.r = r;
+        R.centre[0] = cx / nm;
+        R.centre[1] = cy / nm;
+        R.centre[2] = cz / nm;
+        R.out_off = out_off;
+        R.T = T;
+        R.n_src = rm.n_src;
+        R.n_mic = rm.n_mic;
+        R.src0 = src_row;
+        R.mic0 = mic_row;
+        const double ct = rm.c * rm.rt60;
+        const double log10_r = std::log10(r);
+        const double log10_ct = std::log10(ct);
+        for (int32_t s = 0; s < rm.n_src; ++s) {
+            const double* p = src + 3 * static_cast<int64_t>(src_row + s);
+            if (!finite3(p)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_INVALID_ARG, "room %d source %d: non-finite position", b, s);
+            }
+            if (!strictly_inside(p, rm.size)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_GEOMETRY, "room %d source %d: not strictly inside the room", b, s);
+            }
+            for (int32_t m = 0; m < rm.n_mic; ++m) {
+                const double* q = mics + 3 * m;
+                const double ex = p[0] - q[0], ey = p[1] - q[1], ez = p[2] - q[2];
+                if (!((ex * ex + ey * ey) + ez * ez > 1e-18)) {
+                    delete plan;
+                    return fr_fail(FRAMRIR_E_GEOMETRY, "room %d source %d coincides with mic %d", b, s, m);
+                }
+            }
+            const double dx = p[0] - R.centre[0];
+            const double dy = p[1] - R.centre[1];
+            const double dz = p[2] - R.centre[2];
+            const double d0 = std::sqrt((dx * dx + dy * dy) + dz * dz);
+            if (!(d0 > 0.0)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_GEOMETRY, "room %d source %d: at the array centre (d0 = 0)", b, s);
+            }
+            if (!(d0 < ct)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_GEOMETRY, "room %d source %d: d0 = %g >= c0 T60 = %g", b, s, d0, ct);
+            }
+            SrcDesc S;
+            std::memset(&S, 0, sizeof(S));
+            S.d0 = d0;
+            S.ct = ct;
+            S.q = ct / d0;
+            // Eq. 5, clamped below at 1 (spreading alone may already reach -60 dB)
+            double rr = ((log10_ct - std::log10(d0)) - 3.0) / log10_r;
+            S.rrmax = rr > 1.0 ? rr : 1.0;
+            S.pos[0] = p[0];
+            S.pos[1] = p[1];
+            S.pos[2] = p[2];
+            S.key0 = static_cast<uint32_t>(rm.seed & 0xFFFFFFFFu);
+            S.key1 = static_cast<uint32_t>(rm.seed >> 32);
+            S.room = b;
+            S.s_local = s;
+            // image count from the header counter (0, s, 1, 0)
+            uint32_t x[4] = {0u, static_cast<uint32_t>(s), 1u, 0u};
+            philox4x32_10(x, S.key0, S.key1);
+            const uint64_t span = static_cast<uint64_t>(prm.img_hi - prm.img_lo + 1);
+            const int32_t I = prm.img_lo + static_cast<int32_t>((static_cast<uint64_t>(x[0]) * span) >> 32);
+            S.n_img = I + 1;
+            S.img_off = img_off;
+            img_off += S.n_img;
+            max_img = std::max(max_img, S.n_img);
+            sd.push_back(S);
+        }
+        out_off += static_cast<int64_t>(rm.n_src) * rm.n_mic * T;
+        src_row += rm.n_src;
+        mic_row += rm.n_mic;
+        max_T = std::max(max_T, T);
+    }
+
+    // ---- work items: per source, microphone groups x time tiles
+    std::vector<WorkItem>& it = plan->items;
+    std::vector<double> cost;
+    for (int32_t b = 0; b < n_rooms; ++b) {
+        const RoomDesc& R = rd[b];
+        const int n_groups = (R.n_mic + launch.max_mic_group - 1) / launch.max_mic_group;
+        for (int g = 0; g < n_groups; ++g) {
+            const int m0 = (R.n_mic * g) / n_groups;
+            const int m1 = (R.n_mic * (g + 1)) / n_groups;
+            const int mg = m1 - m0;
+            const int cap = launch.lds_bytes / 4 / mg - 2 * kHalo;
+            if (cap < 64) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_RANGE, "lds_bytes %d too small for %d microphones", launch.lds_bytes, mg);
+            }
+            const int n_tiles = (R.T + cap - 1) / cap;
+            int len = (R.T + n_tiles - 1) / n_tiles;
+            len = (len + 3) & ~3;                       // keep tile starts 16-byte aligned in LDS
+            if (len > cap) len = cap & ~3;
+            const int n_t = (R.T + len - 1) / len;
+            for (int32_t s = 0; s < R.n_src; ++s) {
+                const SrcDesc& S = sd[R.src0 + s];
+                for (int t = 0; t < n_t; ++t) {
+                    WorkItem w;
+                    std::memset(&w, 0, sizeof(w));
+                    w.src = R.src0 + s;
+                    w.mic0 = m0;
+                    w.n_mic = mg;
+                    w.t0 = t * len;
+                    w.len = len;
+                    w.full = n_t == 1 ? 1 : 0;
+                    it.push_back(w);
+                    cost.push_back(static_cast<double>(S.n_img) * mg / n_t + 0.05 * len * mg);
+                }
+            }
+        }
+    }
+    // longest first (stable), so the dynamic queue of the persistent grid
+    // starts the big items early
+    std::vector<int32_t> order(it.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = static_cast<int32_t>(k);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+    std::vector<WorkItem> sorted(it.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = it[order[k]];
+    it.swap(sorted);
+    // per-room item lists in a fixed order (backward reduction)
+    std::vector<std::vector<int32_t>> per_room(n_rooms);
+    for (size_t k = 0; k < it.size(); ++k) per_room[sd[it[k].src].room].push_back(static_cast<int32_t>(k));
+    plan->room_items.clear();
+    for (int32_t b = 0; b < n_rooms; ++b) {
+        rd[b].item0 = static_cast<int32_t>(plan->room_items.size());
+        rd[b].n_item = static_cast<int32_t>(per_room[b].size());
+        plan->room_items.insert(plan->room_items.end(), per_room[b].begin(), per_room[b].end());
+    }
+
+    // ---- header and blob
+    DescHeader H;
+    std::memset(&H, 0, sizeof(H));
+    H.n_rooms = n_rooms;
+    H.n_src = src_row;
+    H.n_mic = mic_row;
+    H.n_items = static_cast<int32_t>(it.size());
+    H.n_img = img_off;
+    H.out_floats = out_off;
+    H.alpha = prm.alpha;
+    H.beta = prm.beta;
+    H.a = prm.a;
+    H.b = prm.b;
+    H.a3 = (prm.alpha * prm.alpha) * prm.alpha;
+    H.b3 = (prm.beta * prm.beta) * prm.beta;
+    H.beta_minus_alpha = prm.beta - prm.alpha;
+    H.b_minus_a = prm.b - prm.a;
+    H.tau_code = tau_code;
+    H.max_img = max_img;
+    H.max_T = max_T;
+    auto align = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+    H.room_bytes = align(sizeof(DescHeader));
+    H.src_bytes = align(H.room_bytes + static_cast<int64_t>(sizeof(RoomDesc)) * n_rooms);
+    H.item_bytes = align(H.src_bytes + static_cast<int64_t>(sizeof(SrcDesc)) * src_row);
+    H.room_items_bytes = align(H.item_bytes + static_cast<int64_t>(sizeof(WorkItem)) * it.size());
+    const int64_t total = align(H.room_items_bytes + static_cast<int64_t>(sizeof(int32_t)) * plan->room_items.size());
+    plan->blob.assign(static_cast<size_t>(total), 0);
+    char* base = plan->blob.data();
+    std::memcpy(base, &H, sizeof(H));
+    std::memcpy(base + H.room_bytes, rd.data(), sizeof(RoomDesc) * rd.size());
+    std::memcpy(base + H.src_bytes, sd.data(), sizeof(SrcDesc) * sd.size());
+    std::memcpy(base + H.item_bytes, it.data(), sizeof(WorkItem) * it.size());
+    std::memcpy(base + H.room_items_bytes, plan->room_items.data(), sizeof(int32_t) * plan->room_items.size());
+    plan->header = H;
+
+    // ---- workspace
+    plan->ws_bytes = kWsCounterBytes;
+    plan->ws_bwd_bytes = kWsCounterBytes + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
+    int32_t grid = launch.grid_wgs;
+    if (grid == 0) {
+        const int per_cu = std::max(1, kMaxAccLdsBytes / launch.lds_bytes);
+        grid = std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu);
+    }
+    plan->grid = std::max(1, grid);
+    *out = plan;
+    return FRAMRIR_OK;
+}
+
+extern "C" void framrir_plan_destroy(framrir_plan* plan) { delete plan; }
+
+extern "C" int framrir_plan_get_info(const framrir_plan* plan, framrir_plan_info* info) {
+    if (!plan || !info) return fr_fail(FRAMRIR_E_INVALID_ARG, "plan and info must be non-NULL");
+    const DescHeader& H = plan->header;
+    info->n_rooms = H.n_rooms;
+    info->n_src = H.n_src;
+    info->n_mic = H.n_mic;
+    info->n_items = H.n_items;
+    info->n_img = H.n_img;
+    info->out_floats = H.out_floats;
+    info->desc_bytes = static_cast<int64_t>(plan->blob.size());
+    info->ws_bytes = plan->ws_bytes;
+    info->ws_bwd_bytes = plan->ws_bwd_bytes;
+    info->max_T = H.max_T;
+    info->max_img = H.max_img;
+    return FRAMRIR_OK;
+}
+
+extern "C" int framrir_plan_get_arrays(const framrir_plan* plan, int32_t* T, int64_t* out_off, double* r,
+                                       int32_t* n_img, int64_t* img_off, double* rrmax, double* d0) {
+    if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "plan is NULL");
+    const DescHeader& H = plan->header;
+    for (int32_t b = 0; b < H.n_rooms; ++b) {
+        if (T) T[b] = plan->rooms[b].T;
+        if (out_off) out_off[b] = plan->rooms[b].out_off;
+        if (r) r[b] = plan->rooms[b].r;
+    }
+    if (out_off) out_off[H.n_rooms] = H.out_floats;
+    for (int32_t s = 0; s < H.n_src; ++s) {
+        if (n_img) n_img[s] = plan->srcs[s].n_img;
+        if (img_off) img_off[s] = plan->srcs[s].img_off;
+        if (rrmax) rrmax[s] = plan->srcs[s].rrmax;
+        if (d0) d0[s] = plan->srcs[s].d0;
+    }
+    if (img_off) img_off[H.n_src] = H.n_img;
+    return FRAMRIR_OK;
+}
+
+extern "C" const void* framrir_plan_desc(const framrir_plan* plan) {
+    return plan ? static_cast<const void*>(plan->blob.data()) : nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// Host builds of the draw-stage numerics, for checks on machines without a GPU
+// ---------------------------------------------------------------------------
+extern "C" int framrir_host_cbrt_rn(const double* x, double* y, int64_t n) {
+    if (!x || !y || n < 0) return fr_fail(FRAMRIR_E_INVALID_ARG, "bad arguments");
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = x[i];
+        y[i] = (v >= 2.2250738585072014e-308 && std::isfinite(v)) ? cbrt_rn(v) : (v == 0.0 ? 0.0 : NAN);
+    }
+    return FRAMRIR_OK;
+}
+
+extern "C" int framrir_host_sqrt_rn(const double* x, double* y, int64_t n) {
+    if (!x || !y || n < 0) return fr_fail(FRAMRIR_E_INVALID_ARG, "bad arguments");
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = x[i];
+        y[i] = (v >= 2.2250738585072014e-308 && std::isfinite(v)) ? sqrt_rn(v) : NAN;
+    }
+    return FRAMRIR_OK;
+}
+
+extern "C" int framrir_host_philox4x32(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n) {
+    if (!ctr || !key || !out || n < 0) return fr_fail(FRAMRIR_E_INVALID_ARG, "bad arguments");
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t x[4] = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+        philox4x32_10(x, key[2 * i], key[2 * i + 1]);
+        for (int k = 0; k < 4; ++k) out[4 * i + k] = x[k];
+    }
+    return FRAMRIR_OK;
+}

@@ -1,0 +1,331 @@
+"""Python binding of libframrir.so (the C ABI in include/framrir.h).
+
+Argument marshalling only: torch supplies device memory and streams, ctypes
+passes raw pointers.  Every step of the method runs in the library's HIP
+kernels; if the library is missing this module raises instead of falling back.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libframrir.so")
+
+FRAMRIR_TAPS = 81
+
+
+class FramrirError(RuntimeError):
+    def __init__(self, code, detail):
+        super().__init__(f"framrir error {code}: {detail}")
+        self.code = code
+
+
+class Room(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_double * 3), ("rt60", ctypes.c_double), ("fs", ctypes.c_double),
+                ("c", ctypes.c_double), ("r_override", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("n_src", ctypes.c_int32), ("n_mic", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("a", ctypes.c_double),
+                ("b", ctypes.c_double), ("tau", ctypes.c_double), ("img_lo", ctypes.c_int32),
+                ("img_hi", ctypes.c_int32), ("taps", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("lds_bytes", ctypes.c_int32), ("wg_threads", ctypes.c_int32), ("grid_wgs", ctypes.c_int32),
+                ("max_mic_group", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_rooms", ctypes.c_int32), ("n_src", ctypes.c_int32), ("n_mic", ctypes.c_int32),
+                ("n_items", ctypes.c_int32), ("n_img", ctypes.c_int64), ("out_floats", ctypes.c_int64),
+                ("desc_bytes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64), ("ws_bwd_bytes", ctypes.c_int64),
+                ("max_T", ctypes.c_int32), ("max_img", ctypes.c_int32)]
+
+
+DEFAULT_PARAMS = dict(alpha=0.25, beta=1.0, a=-2.0, b=2.0, tau=0.25, img_lo=1024, img_hi=4096)
+DEFAULT_LAUNCH = dict(lds_bytes=131072, wg_threads=1024, grid_wgs=0, max_mic_group=8)
+
+EXPORTS = {
+    "framrir_plan_create": (ctypes.c_int, [ctypes.POINTER(Room), ctypes.c_int32, ctypes.POINTER(Params),
+                                           ctypes.POINTER(Launch), ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "framrir_plan_destroy": (None, [ctypes.c_void_p]),
+    "framrir_plan_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
+    "framrir_plan_get_arrays": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7),
+    "framrir_plan_desc": (ctypes.c_void_p, [ctypes.c_void_p]),
+    "framrir_draw": (ctypes.c_int, [ctypes.c_void_p] * 6),
+    "framrir_render": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_forward": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_render_backward": (ctypes.c_int, [ctypes.c_void_p] * 11 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]),
+    "framrir_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_void_p]),
+    "framrir_host_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64]),
+    "framrir_host_sqrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64]),
+    "framrir_host_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64]),
+    "framrir_last_error_detail": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
+    "framrir_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "framrir_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libframrir.so (built in-tree).  torch is imported first so that
+    the library binds to the HIP runtime torch already loaded."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (HIP runtime first)
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2304_08052_amd.build")
+        so = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(so, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = so
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        buf = ctypes.create_string_buffer(1024)
+        lib().framrir_last_error_detail(buf, 1024)
+        raise FramrirError(rc, buf.value.decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Host plan of a batch plus its descriptor blob on the device.
+
+    batch: dict with size (B,3), rt60, fs, c, r_override, seed, n_src, n_mic,
+    src (sum n_src, 3), mic (sum n_mic, 3) -- see workloads.py."""
+
+    def __init__(self, batch, params=None, launch=None, device="cuda"):
+        """device="cpu" plans and keeps the blob in host memory (no GPU calls)."""
+        import torch
+        L = lib()
+        prm = dict(DEFAULT_PARAMS, **(params or {}))
+        lau = dict(DEFAULT_LAUNCH, **(launch or {}))
+        n = len(batch["rt60"])
+        rooms = (Room * n)()
+        for b in range(n):
+            rm = rooms[b]
+            for k in range(3):
+                rm.size[k] = float(batch["size"][b][k])
+            rm.rt60 = float(batch["rt60"][b])
+            rm.fs = float(batch["fs"][b])
+            rm.c = float(batch["c"][b])
+            rm.r_override = float(batch["r_override"][b])
+            rm.seed = int(batch["seed"][b])
+            rm.n_src = int(batch["n_src"][b])
+            rm.n_mic = int(batch["n_mic"][b])
+        self.src = np.ascontiguousarray(batch["src"], dtype=np.float64)
+        self.mic = np.ascontiguousarray(batch["mic"], dtype=np.float64)
+        p = Params(prm["alpha"], prm["beta"], prm["a"], prm["b"], prm["tau"], prm["img_lo"], prm["img_hi"],
+                   FRAMRIR_TAPS, 0)
+        la = Launch(lau["lds_bytes"], lau["wg_threads"], lau["grid_wgs"], lau["max_mic_group"])
+        handle = ctypes.c_void_p()
+        _check(L.framrir_plan_create(rooms, n, ctypes.byref(p), ctypes.byref(la), _np_ptr(self.src),
+                                     _np_ptr(self.mic), ctypes.byref(handle)))
+        self._h = handle
+        self.params = prm
+        self.launch = lau
+        info = PlanInfo()
+        _check(L.framrir_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+        self.n_rooms = info.n_rooms
+        self.T = np.zeros(n, dtype=np.int32)
+        self.out_off = np.zeros(n + 1, dtype=np.int64)
+        self.r = np.zeros(n, dtype=np.float64)
+        self.n_img = np.zeros(info.n_src, dtype=np.int32)
+        self.img_off = np.zeros(info.n_src + 1, dtype=np.int64)
+        self.rrmax = np.zeros(info.n_src, dtype=np.float64)
+        self.d0 = np.zeros(info.n_src, dtype=np.float64)
+        _check(L.framrir_plan_get_arrays(self._h, _np_ptr(self.T), _np_ptr(self.out_off), _np_ptr(self.r),
+                                         _np_ptr(self.n_img), _np_ptr(self.img_off), _np_ptr(self.rrmax),
+                                         _np_ptr(self.d0)))
+        self.n_src = np.asarray(batch["n_src"], dtype=np.int64)
+        self.n_mic = np.asarray(batch["n_mic"], dtype=np.int64)
+        self.src_off = np.concatenate([[0], np.cumsum(self.n_src)])
+        self.mic_off = np.concatenate([[0], np.cumsum(self.n_mic)])
+        blob = ctypes.string_at(L.framrir_plan_desc(self._h), info.desc_bytes)
+        self.device = torch.device(device)
+        self.desc = torch.from_numpy(np.frombuffer(blob, dtype=np.uint8).copy()).to(self.device)
+        self.src_dev = torch.from_numpy(self.src).to(self.device)
+        self.mic_dev = torch.from_numpy(self.mic).to(self.device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.framrir_plan_destroy(h)
+            self._h = None
+
+    # ---- buffers -----------------------------------------------------------
+    def empty_table(self):
+        import torch
+        return torch.empty((self.info.n_img, 4), dtype=torch.float64, device=self.device)
+
+    def empty_out(self):
+        import torch
+        return torch.empty(self.info.out_floats, dtype=torch.float32, device=self.device)
+
+    def workspace(self, backward=False):
+        import torch
+        n = self.info.ws_bwd_bytes if backward else self.info.ws_bytes
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    # ---- device calls ------------------------------------------------------
+    def draw(self, table=None, aux=False, words=False, stream=None):
+        import torch
+        table = self.empty_table() if table is None else table
+        aux_t = torch.empty((self.info.n_img, 8), dtype=torch.float64, device=self.device) if aux else None
+        w_t = torch.empty((self.info.n_img, 4), dtype=torch.int32, device=self.device) if words else None
+        _check(lib().framrir_draw(self._h, _ptr(self.desc), _ptr(table), _ptr(aux_t), _ptr(w_t),
+                                  _stream(stream)))
+        return table, aux_t, w_t
+
+    def render(self, table, mic=None, src=None, r=None, out=None, ws=None, stream=None):
+        out = self.empty_out() if out is None else out
+        ws = self.workspace() if ws is None else ws
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        _check(lib().framrir_render(self._h, _ptr(self.desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                    _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def forward(self, table=None, mic=None, src=None, r=None, out=None, ws=None, stream=None):
+        table = self.empty_table() if table is None else table
+        out = self.empty_out() if out is None else out
+        ws = self.workspace() if ws is None else ws
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        _check(lib().framrir_forward(self._h, _ptr(self.desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                     _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out, table
+
+    def backward(self, table, grad_out, mic=None, src=None, r=None, ws=None, grads=None, stream=None):
+        import torch
+        ws = self.workspace(backward=True) if ws is None else ws
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        if grads is None:
+            grads = (torch.empty((self.info.n_mic, 3), dtype=torch.float32, device=self.device),
+                     torch.empty((self.info.n_src, 3), dtype=torch.float32, device=self.device),
+                     torch.empty(self.info.n_rooms, dtype=torch.float32, device=self.device))
+        gm, gs, gr = grads
+        _check(lib().framrir_render_backward(self._h, _ptr(self.desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                             _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws), ws.numel(),
+                                             _stream(stream)))
+        return gm, gs, gr
+
+    # ---- views -------------------------------------------------------------
+    def room_view(self, out, b):
+        """[S_b, M_b, T_b] view of room b in the packed output."""
+        s, m, t = int(self.n_src[b]), int(self.n_mic[b]), int(self.T[b])
+        o = int(self.out_off[b])
+        return out[o:o + s * m * t].view(s, m, t)
+
+    def source_rows(self, table, s):
+        """Image-table rows of global source s."""
+        return table[int(self.img_off[s]):int(self.img_off[s + 1])]
+
+
+def philox4x32(ctr, key, stream=None):
+    """Device Philox4x32-10: ctr int32 [n,4], key int32 [n,2] (bit patterns)."""
+    import torch
+    out = torch.empty_like(ctr)
+    _check(lib().framrir_philox4x32(_ptr(ctr), _ptr(key), _ptr(out), ctr.shape[0], _stream(stream)))
+    return out
+
+
+def cbrt_rn(x, stream=None):
+    """Device correctly rounded cube root of an FP64 tensor."""
+    import torch
+    y = torch.empty_like(x)
+    _check(lib().framrir_cbrt_rn(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
+    return y
+
+
+def host_cbrt_rn(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(x)
+    _check(lib().framrir_host_cbrt_rn(_np_ptr(x), _np_ptr(y), x.size))
+    return y
+
+
+def host_sqrt_rn(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(x)
+    _check(lib().framrir_host_sqrt_rn(_np_ptr(x), _np_ptr(y), x.size))
+    return y
+
+
+def host_philox4x32(ctr, key):
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32)
+    key = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty_like(ctr)
+    _check(lib().framrir_host_philox4x32(_np_ptr(ctr), _np_ptr(key), _np_ptr(out), ctr.shape[0]))
+    return out
+
+
+def simulate(batch, params=None, launch=None):
+    """Batched forward: returns (packed FP32 RIRs on the device, plan, table)."""
+    plan = Plan(batch, params, launch)
+    out, table = plan.forward()
+    return out, plan, table
+
+
+def _autograd():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        """Render with the image table held fixed; differentiable in the
+        microphone positions, source positions and per-room r."""
+
+        @staticmethod
+        def forward(ctx, mic, src, r, plan, table):
+            out = plan.render(table, mic=mic.contiguous(), src=src.contiguous(), r=r.contiguous())
+            ctx.plan = plan
+            ctx.table = table
+            ctx.save_for_backward(mic, src, r)
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            mic, src, r = ctx.saved_tensors
+            gm, gs, gr = ctx.plan.backward(ctx.table, grad_out.contiguous().float(), mic=mic.contiguous(),
+                                           src=src.contiguous(), r=r.contiguous())
+            return gm.to(mic.dtype), gs.to(src.dtype), gr.to(r.dtype), None, None
+
+    return RenderFn
+
+
+_RENDER_FN = None
+
+
+def render_differentiable(plan, table, mic, src, r):
+    """Autograd entry: RIRs as a function of mic [n_mic,3], src [n_src,3]
+    and r [n_rooms] (FP64 tensors), draws held fixed."""
+    global _RENDER_FN
+    if _RENDER_FN is None:
+        _RENDER_FN = _autograd()
+    return _RENDER_FN.apply(mic, src, r, plan, table)

@@ -1,0 +1,161 @@
+"""CPU checks of the C-ABI library: it loads, exports every function
+include/framrir.h declares, its host builds of the draw-stage numerics equal
+the oracle bit for bit, its planner's per-room / per-source scalars equal the
+oracle's bit for bit, and invalid inputs map to the documented error codes.
+No device calls."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import framrir as F
+from oracle.cbrt import cbrt_rn as oracle_cbrt
+from oracle.philox import philox4x32 as oracle_philox
+from paper_2304_08052_amd import framrir as fr
+from paper_2304_08052_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "framrir.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(framrir_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _header_functions()
+    assert len(names) >= 15
+    so = ctypes.CDLL(fr.LIB_PATH)
+    missing = [n for n in names if not hasattr(so, n)]
+    assert not missing, missing
+    assert set(names) <= set(fr.EXPORTS)
+
+
+def test_version_and_strerror():
+    L = fr.lib()
+    assert L.framrir_version() >> 16 == 1
+    assert L.framrir_strerror(-2) == b"invalid geometry"
+
+
+def test_host_cbrt_bit_exact_vs_oracle():
+    rng = np.random.default_rng(0)
+    u = (rng.integers(0, 2**32, 20000).astype(np.float64) + 0.5) * 2.0**-32
+    args = [1.0 / 64.0 + u * (63.0 / 64.0),          # the default alpha, beta
+            u,                                      # alpha = 0
+            10.0 ** rng.uniform(-300, 300, 5000),
+            np.array([1.0, 8.0, 27.0, 0.125, 2.0, 3.0, 1e-300, 1.7976931348623157e308])]
+    for a in args:
+        got = fr.host_cbrt_rn(a)
+        want = np.array([oracle_cbrt(float(v)) for v in a])
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_host_sqrt_correctly_rounded():
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.uniform(1.0, 4000.0, 50000), 10.0 ** rng.uniform(-300, 300, 20000)])
+    assert np.array_equal(fr.host_sqrt_rn(x).view(np.uint64), np.sqrt(x).view(np.uint64))
+
+
+def test_host_philox_bit_exact_vs_oracle():
+    rng = np.random.default_rng(2)
+    ctr = rng.integers(0, 2**32, (20000, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, (20000, 2), dtype=np.uint64).astype(np.uint32)
+    got = fr.host_philox4x32(ctr, key)
+    want = np.stack(oracle_philox(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3], key[:, 0], key[:, 1]), axis=1)
+    assert np.array_equal(got.astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("maker", [W.config1, lambda: W.config2(16), lambda: W.config3(4),
+                                   lambda: W.small_mixed(8, seed=3)])
+def test_plan_scalars_bit_equal_oracle(maker):
+    batch = maker()
+    plan = fr.Plan(batch, device="cpu")
+    prm = F.Params()
+    rooms = F.rooms_from_batch(batch)
+    s_glob = 0
+    for b, rm in enumerate(rooms):
+        assert plan.T[b] == F.rir_length(rm.rt60, rm.fs)
+        r = F.eyring_r(rm.size, rm.rt60)
+        assert plan.r[b] == r
+        centre = F.array_centre(rm.mic)
+        for s in range(len(rm.src)):
+            d0, ct, q, rr = F.source_scalars(rm.src[s], centre, rm.c, rm.rt60, r)
+            assert plan.d0[s_glob] == d0
+            assert plan.rrmax[s_glob] == rr
+            assert plan.n_img[s_glob] == F.num_images(rm.seed, s, prm) + 1
+            s_glob += 1
+    # packed offsets
+    sizes = [int(batch["n_src"][b]) * int(batch["n_mic"][b]) * int(plan.T[b]) for b in range(len(rooms))]
+    assert np.array_equal(np.diff(plan.out_off), sizes)
+    assert plan.info.out_floats == sum(sizes)
+    assert plan.info.n_img == int(plan.n_img.sum())
+
+
+def _bad(batch, **kw):
+    b = {k: np.array(v, copy=True) for k, v in batch.items()}
+    for k, v in kw.items():
+        b[k] = v(b) if callable(v) else v
+    return b
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (dict(rt60=np.array([-0.4])), -3),
+    (dict(fs=np.array([0.0])), -3),
+    (dict(size=np.array([[6.0, 0.0, 3.0]])), -2),
+    (dict(src=np.array([[7.0, 3.0, 1.5]])), -2),                  # outside the room
+    (dict(mic=lambda b: np.array([[3.975, 2.5, 1.2], [4.025, 2.5, 3.5]])), -2),
+    (dict(src=np.array([[3.975, 2.5, 1.2]])), -2),                # on a microphone
+    (dict(r_override=np.array([1.0])), -3),
+    (dict(rt60=np.array([np.nan])), -1),
+    (dict(rt60=np.array([0.005])), -2),                           # d0 >= c0 T60
+])
+def test_invalid_inputs_rejected(mutate, code):
+    with pytest.raises(fr.FramrirError) as ei:
+        fr.Plan(_bad(W.config1(), **mutate), device="cpu")
+    assert ei.value.code == code
+
+
+@pytest.mark.parametrize("params,code", [
+    (dict(alpha=0.5, beta=0.5), -3), (dict(tau=0.3), -3), (dict(a=1.0, b=0.0), -3),
+    (dict(img_lo=10, img_hi=5), -3), (dict(img_hi=70000), -3)])
+def test_invalid_params_rejected(params, code):
+    with pytest.raises(fr.FramrirError) as ei:
+        fr.Plan(W.config1(), params=params, device="cpu")
+    assert ei.value.code == code
+
+
+def test_invalid_launch_rejected():
+    with pytest.raises(fr.FramrirError):
+        fr.Plan(W.config1(), launch=dict(wg_threads=100), device="cpu")
+    with pytest.raises(fr.FramrirError):
+        fr.Plan(W.config1(), launch=dict(lds_bytes=1000000), device="cpu")
+
+
+def test_work_items_cover_every_output_once():
+    # time tiles x microphone groups of every source partition [0, T) x mics
+    batch = W.small_mixed(6, seed=11)
+    plan = fr.Plan(batch, launch=dict(lds_bytes=32768, wg_threads=1024, max_mic_group=3), device="cpu")
+    blob = plan.desc.numpy().tobytes()
+    hdr = np.frombuffer(blob[:256], dtype=np.int64)
+    n_items = int(np.frombuffer(blob[:16], dtype=np.int32)[3])
+    item_bytes = int(hdr[6])          # int32 x4, n_img, out_floats, room_bytes, src_bytes, item_bytes
+    items = np.frombuffer(blob[item_bytes:item_bytes + 32 * n_items], dtype=np.int32).reshape(n_items, 8)
+    cover = {}
+    for src, m0, nm, t0, ln, full, _, _ in items:
+        for m in range(m0, m0 + nm):
+            cover.setdefault((src, m), []).append((t0, ln))
+    s_glob = 0
+    for b in range(plan.n_rooms):
+        for s in range(int(plan.n_src[b])):
+            for m in range(int(plan.n_mic[b])):
+                tiles = sorted(cover[(s_glob, m)])
+                pos = 0
+                for t0, ln in tiles:
+                    assert t0 == pos
+                    pos += ln
+                assert pos >= plan.T[b] and pos - tiles[-1][1] < plan.T[b]
+            s_glob += 1
