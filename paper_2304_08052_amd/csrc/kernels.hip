@@ -5,7 +5,8 @@
 //   render_kernel    Eq. 1, 8: persistent grid over work items (source,
 //                    microphone group, time tile); per (image, microphone) pair
 //                    an FP64 delay, then 81 windowed-sinc taps accumulated in an
-//                    LDS tile with ds_add_f32; coalesced writeback.
+//                    LDS tile as fixed-point integers (ds_add_u32) under a
+//                    per-row scale that cannot overflow; coalesced writeback.
 //   backward_kernel  adjoint of the render with the image table held fixed:
 //                    per pair 81-tap dot products of dL/dh with P and P'.
 //   finalize_kernel  fixed-order reduction of the backward partials.
@@ -170,14 +171,18 @@ __device__ __forceinline__ Pair pair_setup(double px, double py, double pz, doub
 // ---- forward taps.  With m = j - 40, x = m - dl and S = A sin(pi dl)/pi:
 //   A P(x) = (-1)^(m+1) S cos^2(pi x / 81) / x.
 // cos(pi x/81) = cos(pi m/81) cos(pi dl/81) + sin(pi m/81) sin(pi dl/81).
-// sqrt(|S|) is folded into the two per-pair factors and sign(S) (-1)^(m+1)
-// into the divisor, so a tap costs one FMA for the divisor, one rcp, two for
-// the window and two multiplies.
+// sqrt(|S| scale) is folded into the two per-pair factors and sign(S)
+// (-1)^(m+1) into the divisor, so a tap costs one FMA for the divisor, one
+// rcp, two for the window, two multiplies and a round-to-integer.  The tile
+// accumulates fixed-point integers with ds_add_u32: gfx950 runs LDS integer
+// atomics ~20x faster than FP32 ones, and integer sums do not depend on the
+// order of the additions, so the output is bitwise reproducible.
 template <int J>
-__device__ __forceinline__ void fwd_tap(float* __restrict__ row, float cd, float sd, float sig, float sdl, float v0) {
+__device__ __forceinline__ void fwd_tap(int* __restrict__ row, float cd, float sd, float sig, float sdl, float v0) {
     constexpr int m = J - kHalf;
+    float v;
     if constexpr (m == 0) {
-        atomicAdd(row + J, v0);
+        v = v0;
     } else {
         constexpr float M = static_cast<float>(m);
         constexpr float C = static_cast<float>(ct_cos(kPiOver81 * m));
@@ -185,12 +190,13 @@ __device__ __forceinline__ void fwd_tap(float* __restrict__ row, float cd, float
         const float x = (m & 1) ? __builtin_fmaf(sig, M, -sdl) : __builtin_fmaf(-sig, M, sdl);
         const float rx = __builtin_amdgcn_rcpf(x);
         const float c = __builtin_fmaf(C, cd, Sn * sd);
-        atomicAdd(row + J, (c * c) * rx);
+        v = (c * c) * rx;
     }
+    atomicAdd(row + J, static_cast<int>(__builtin_rintf(v)));
 }
 
 template <int... J>
-__device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, float* __restrict__ row, float cd,
+__device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, int* __restrict__ row, float cd,
                                          float sd, float sig, float sdl, float v0) {
     (fwd_tap<J>(row, cd, sd, sig, sdl, v0), ...);
 }
@@ -341,14 +347,30 @@ __device__ int compact_rows(const ItemCtx& c, int seg0, int seg1, const double* 
 // ---------------------------------------------------------------------------
 // Render
 // ---------------------------------------------------------------------------
+// Fixed-point budget of one LDS accumulator: the sum of |tap| over every pair
+// of a row bounds |sample|, since the pulse never exceeds 1 in magnitude;
+// the bound plus the per-add rounding slack is mapped just below 2^31.
+constexpr float kFixedBudget = 2147483648.0f - 262144.0f;
+constexpr float kBoundMargin = 1.0001f;
+
+// Upper bound of A = r^g / D for one pair, in FP32 (used only for the scale).
+__device__ __forceinline__ float pair_amp_bound(double px, double py, double pz, double mx, double my, double mz,
+                                                float amp) {
+    const float dx = static_cast<float>(px - mx), dy = static_cast<float>(py - my), dz = static_cast<float>(pz - mz);
+    const float d = __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+    return amp / d;
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ desc, const double* __restrict__ table,
                                                      const double* __restrict__ mic, const double* __restrict__ src,
                                                      const double* __restrict__ r_in, float* __restrict__ out,
                                                      int* __restrict__ counters) {
-    extern __shared__ float acc[];
+    extern __shared__ int acc[];
     __shared__ int list[kListCap];
     __shared__ int wave_cnt[NT / 64];
+    __shared__ float bound[NT];
+    __shared__ float row_scale[kMaxMicGroup];
     __shared__ int s_item;
     const DescHeader* H = hdr(desc);
     const int n_items = H->n_items;
@@ -362,15 +384,42 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
         load_item(desc, item, mic, r_in, c);
         const int mg = c.w.n_mic;
         const int nacc = mg * c.rowlen;
-        for (int k = tid; k < nacc; k += NT) acc[k] = 0.0f;
+        for (int k = tid; k < nacc; k += NT) acc[k] = 0;
         // this thread's microphone and image slot
         const int ipp = NT / mg;
         const int my_m = tid % mg, my_slot = tid / mg;
         const double* mq = mic + 3 * (c.mic0_glob + my_m);
         const double mx = mq[0], my = mq[1], mz = mq[2];
-        float* row = acc + my_m * c.rowlen;
+        int* row = acc + my_m * c.rowlen;
         const int shift = kHalo - kHalf - c.w.t0;   // LDS index of tap 0 = k + shift
+        // ---- pass 1: per-row bound of the sum of |taps| (fixed thread order)
+        float bsum = 0.0f;
+        for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
+            const int seg1 = min(c.n_img, seg0 + kListCap);
+            int n_list = seg1 - seg0;
+            if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
+            if (my_slot < ipp) {
+                for (int e = my_slot; e < n_list; e += ipp) {
+                    const int i = c.w.full ? seg0 + e : list[e];
+                    double px, py, pz, g;
+                    image_row(c, i, table, src, c.w.src, px, py, pz, g);
+                    const float amp = exp2f(static_cast<float>(g * c.log2r));
+                    bsum += pair_amp_bound(px, py, pz, mx, my, mz, amp);
+                }
+            }
+            __syncthreads();
+        }
+        bound[tid] = bsum;
         __syncthreads();
+        if (tid < mg) {
+            float b = 0.0f;
+            for (int t = tid; t < ipp * mg; t += mg) b += bound[t];
+            b *= kBoundMargin;
+            row_scale[tid] = b > 0.0f ? kFixedBudget / b : 1.0f;
+        }
+        __syncthreads();
+        const float scale = row_scale[my_m];
+        // ---- pass 2: scatter the taps as rounded fixed-point integers
         for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
             const int seg1 = min(c.n_img, seg0 + kListCap);
             int n_list = seg1 - seg0;
@@ -384,12 +433,12 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
                     const Pair P = pair_setup(px, py, pz, mx, my, mz, c.fs_over_c, amp);
                     const int b0 = P.k + shift;
                     if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
-                    const float aS = fabsf(P.S);
+                    const float aS = fabsf(P.S) * scale;
                     const float sq = __builtin_sqrtf(aS);
                     const float cd = sq * P.cy, sd = sq * P.sy;
                     const float sig = P.S < 0.0f ? -1.0f : 1.0f;
                     const float sdl = sig * P.dl;
-                    const float v0 = P.A * P.sinc * (P.cy * P.cy);
+                    const float v0 = (P.A * scale) * P.sinc * (P.cy * P.cy);
                     fwd_taps(std::make_integer_sequence<int, kTaps>{}, row + b0, cd, sd, sig, sdl, v0);
                 }
             }
@@ -400,8 +449,9 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
         for (int m = 0; m < mg; ++m) {
             float* dst = out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + m) * c.T +
                          c.w.t0;
-            const float* srcrow = acc + m * c.rowlen + kHalo;
-            for (int n = tid; n < nvalid; n += NT) dst[n] = srcrow[n];
+            const int* srcrow = acc + m * c.rowlen + kHalo;
+            const float inv = 1.0f / row_scale[m];
+            for (int n = tid; n < nvalid; n += NT) dst[n] = static_cast<float>(srcrow[n]) * inv;
         }
         __syncthreads();
     }
@@ -625,11 +675,17 @@ extern "C" int framrir_draw(const framrir_plan* plan, const void* desc_dev, doub
 
 namespace {
 
+// Raises a kernel's dynamic-LDS limit to the largest budget a plan may use,
+// once per kernel and process (the attribute is not a stream operation).
 template <typename F>
-int allow_lds(F kernel, int bytes) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return fr_fail(FRAMRIR_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+int allow_lds(F kernel) {
+    static int status = [&] {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxAccLdsBytes);
+        return e == hipSuccess ? 0 : static_cast<int>(e);
+    }();
+    if (status != 0)
+        return fr_fail(FRAMRIR_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(static_cast<hipError_t>(status)));
     return FRAMRIR_OK;
 }
 
@@ -640,7 +696,7 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
     switch (plan->launch.wg_threads) {
 #define FR_CASE(NT)                                                                                         \
     case NT:                                                                                                \
-        if (int rc = allow_lds(render_kernel<NT>, lds)) return rc;                                          \
+        if (int rc = allow_lds(render_kernel<NT>)) return rc;                                                  \
         hipLaunchKernelGGL(render_kernel<NT>, grid, block, lds, st, desc_dev, table_dev, mic_dev, src_dev, \
                            r_dev, out_dev, counters);                                                       \
         break;
@@ -714,7 +770,7 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
     switch (plan->launch.wg_threads) {
 #define FR_CASE(NT)                                                                                           \
     case NT:                                                                                                  \
-        if (int rc2 = allow_lds(backward_kernel<NT>, lds)) return rc2;                                        \
+        if (int rc2 = allow_lds(backward_kernel<NT>)) return rc2;                                              \
         hipLaunchKernelGGL(backward_kernel<NT>, grid, block, lds, st, desc_dev, table_dev, mic_dev, src_dev, \
                            r_dev, grad_out_dev, partials, counters);                                          \
         break;

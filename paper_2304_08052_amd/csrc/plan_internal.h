@@ -8,8 +8,8 @@
 #include "framrir_internal.h"
 
 // Largest LDS accumulator budget per workgroup: 160 000 B of gfx950 LDS minus
-// the compacted image list and reduction scratch.
-constexpr int kMaxAccLdsBytes = 160000 - 4 * framrir::kListCap - 2048;
+// the compacted image list, the bound reduction and small scratch.
+constexpr int kMaxAccLdsBytes = 160000 - 4 * framrir::kListCap - 6144;
 // Workspace header: work-queue and completion counters of the persistent grid.
 constexpr int64_t kWsCounterBytes = 256;
 

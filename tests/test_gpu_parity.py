@@ -218,3 +218,17 @@ def test_output_fully_written():
     b = plan.render(table, out=torch.full((plan.info.out_floats,), 7.0, device="cuda"))
     assert torch.isfinite(a).all()
     assert torch.allclose(a, b, rtol=1e-6, atol=1e-9)
+
+
+def test_forward_bitwise_reproducible():
+    # fixed-point accumulation: the result does not depend on the order in
+    # which the workgroups' atomics land
+    torch, fr = _torch(), _fr()
+    say("forward determinism")
+    batch = W.config2(32)
+    plan = fr.Plan(batch)
+    table, _, _ = plan.draw()
+    a = plan.render(table).clone()
+    b = plan.render(table).clone()
+    c = fr.Plan(batch, launch=dict(grid_wgs=13)).render(table)
+    assert torch.equal(a, b) and torch.equal(a, c)
