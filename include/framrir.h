@@ -175,8 +175,11 @@ int framrir_draw(const framrir_plan* plan, const void* desc_dev, double* table_d
  * (row 0 of each source is taken from src_dev, the other rows from the
  * table).  r_dev [n_rooms] FP64 or NULL (= the plan's r).  out_dev:
  * out_floats FP32, 16-byte aligned.  ws_dev: ws_bytes of device memory,
- * 256-byte aligned, contents need not be initialised.  Errors: INVALID_ARG,
- * WORKSPACE, DEVICE. */
+ * 256-byte aligned, initialised once by framrir_workspace_init (or zero
+ * filled); every call leaves it initialised again.  Calls that share a
+ * workspace must not overlap.  Samples are accumulated as fixed-point
+ * integers under a per-row scale that bounds the row's magnitude, so the
+ * result is bitwise reproducible.  Errors: INVALID_ARG, WORKSPACE, DEVICE. */
 int framrir_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
                    const double* mic_dev, const double* src_dev, const double* r_dev,
                    float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
@@ -193,11 +196,16 @@ int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* tabl
  *   dL/dsrc_s = -(the same sum over row 0 only)          -> grad_src_dev [n_src][3]
  *   dL/dr_b   = sum_{s,m,i} (g_i / r) A S0                -> grad_r_dev [n_rooms]
  * Outputs are FP32 and fully overwritten; any may be NULL.  Sums run in a
- * fixed order, so results are bitwise reproducible.  ws_dev: ws_bwd_bytes. */
+ * fixed order, so results are bitwise reproducible.  ws_dev: ws_bwd_bytes,
+ * initialised as for framrir_render. */
 int framrir_render_backward(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
                             const double* mic_dev, const double* src_dev, const double* r_dev,
                             const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
                             float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Initialises the counters at the start of a render / backward workspace
+ * (enqueues one small kernel; no host synchronisation). */
+int framrir_workspace_init(void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Philox4x32-10 (Salmon et al., SC'11) of n counters: ctr_dev [n][4],
  * key_dev [n][2], out_dev [n][4] (uint32, device).  Test export of the

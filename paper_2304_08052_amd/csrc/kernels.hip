@@ -21,6 +21,7 @@
 #include "../../include/framrir.h"
 #include "framrir_internal.h"
 #include "plan_internal.h"
+#include "tap_poly.h"
 
 using namespace framrir;
 
@@ -168,37 +169,60 @@ __device__ __forceinline__ Pair pair_setup(double px, double py, double pz, doub
     return P;
 }
 
-// ---- forward taps.  With m = j - 40, x = m - dl and S = A sin(pi dl)/pi:
-//   A P(x) = (-1)^(m+1) S cos^2(pi x / 81) / x.
-// cos(pi x/81) = cos(pi m/81) cos(pi dl/81) + sin(pi m/81) sin(pi dl/81).
-// sqrt(|S| scale) is folded into the two per-pair factors and sign(S)
-// (-1)^(m+1) into the divisor, so a tap costs one FMA for the divisor, one
-// rcp, two for the window, two multiplies and a round-to-integer.  The tile
-// accumulates fixed-point integers with ds_add_u32: gfx950 runs LDS integer
-// atomics ~20x faster than FP32 ones, and integer sums do not depend on the
-// order of the additions, so the output is bitwise reproducible.
-template <int J>
-__device__ __forceinline__ void fwd_tap(int* __restrict__ row, float cd, float sd, float sig, float sdl, float v0) {
-    constexpr int m = J - kHalf;
-    float v;
-    if constexpr (m == 0) {
-        v = v0;
+// ---- forward taps.  With m = j - 40 and S = A sin(pi dl) / pi,
+//   A P(m - dl) = S Q_m(dl),  Q_m(dl) = (-1)^(m+1) cos^2(pi (m - dl)/81) / (m - dl).
+// For |m| >= 3, Q_m is a short polynomial in dl (tap_poly.h); the taps next to
+// the centre keep the quotient, with cos(pi (m - dl)/81) from the angle-sum
+// identity; m = 0 is A sinc(dl) cos^2(pi dl/81), computed per pair.  Values
+// arrive pre-scaled to fixed point; +1/2 and floor round them to integers.
+// The tile accumulates them with ds_add_u32: gfx950 runs LDS integer atomics
+// ~20x faster than FP32 ones, and integer sums do not depend on the order of
+// the additions, so the output is bitwise reproducible.
+template <int J, int K>
+__device__ __forceinline__ float tap_horner(float dl) {
+    constexpr float c = kPolyCoef[J][K];
+    if constexpr (K == kPolyDeg[J]) {
+        return c;
     } else {
+        return __builtin_fmaf(tap_horner<J, K + 1>(dl), dl, c);
+    }
+}
+
+// floor(v) as int32 in one VOP1 instruction (register operands only).
+__device__ __forceinline__ int cvt_floor_i32(float v) {
+    int q;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(q) : "v"(v));
+    return q;
+}
+
+// Fixed-point tap value plus 1/2 (the caller floors it: round to nearest).
+template <int J>
+__device__ __forceinline__ float tap_value_half(float dl, float S, float cy, float sy, float v0h) {
+    constexpr int m = J - kHalf;
+    if constexpr (m == 0) {
+        return v0h;
+    } else if constexpr (kPolyDeg[J] < 0) {
         constexpr float M = static_cast<float>(m);
         constexpr float C = static_cast<float>(ct_cos(kPiOver81 * m));
         constexpr float Sn = static_cast<float>(ct_sin(kPiOver81 * m));
-        const float x = (m & 1) ? __builtin_fmaf(sig, M, -sdl) : __builtin_fmaf(-sig, M, sdl);
-        const float rx = __builtin_amdgcn_rcpf(x);
-        const float c = __builtin_fmaf(C, cd, Sn * sd);
-        v = (c * c) * rx;
+        constexpr float sgn = (m & 1) ? 1.0f : -1.0f;       // (-1)^(m+1)
+        const float rx = __builtin_amdgcn_rcpf(M - dl);
+        const float cw = __builtin_fmaf(C, cy, Sn * sy);
+        return __builtin_fmaf(S, (sgn * (cw * cw)) * rx, 0.5f);
+    } else {
+        return __builtin_fmaf(S, tap_horner<J, 0>(dl), 0.5f);
     }
-    atomicAdd(row + J, static_cast<int>(__builtin_rintf(v)));
+}
+
+template <int J>
+__device__ __forceinline__ void fwd_tap(int* __restrict__ row, float dl, float S, float cy, float sy, float v0h) {
+    atomicAdd(row + J, cvt_floor_i32(tap_value_half<J>(dl, S, cy, sy, v0h)));
 }
 
 template <int... J>
-__device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, int* __restrict__ row, float cd,
-                                         float sd, float sig, float sdl, float v0) {
-    (fwd_tap<J>(row, cd, sd, sig, sdl, v0), ...);
+__device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, int* __restrict__ row, float dl, float S,
+                                         float cy, float sy, float v0) {
+    (fwd_tap<J>(row, dl, S, cy, sy, v0), ...);
 }
 
 // ---- backward taps: s0 += G A P(x), s1 += G A P'(x) with
@@ -259,6 +283,7 @@ struct ItemCtx {
     double fs_over_c, cx, cy, cz;
     double r, log2r;
     float margin;   // max |mic - centre| fs / c + 2 samples, for the tile test
+    float rho;      // max |mic - centre| of the group (metres)
 };
 
 __device__ __forceinline__ void load_item(const void* desc, int item, const double* __restrict__ mic,
@@ -288,6 +313,7 @@ __device__ __forceinline__ void load_item(const void* desc, int item, const doub
         mx = fmax(mx, __builtin_sqrt(ex * ex + ey * ey + ez * ez));
     }
     c.margin = static_cast<float>(mx * c.fs_over_c) + 2.0f;
+    c.rho = static_cast<float>(mx) * 1.000001f + 1e-7f;
 }
 
 // Image position / reflection count of table row i (row 0 follows src).
@@ -347,18 +373,30 @@ __device__ int compact_rows(const ItemCtx& c, int seg0, int seg1, const double* 
 // ---------------------------------------------------------------------------
 // Render
 // ---------------------------------------------------------------------------
-// Fixed-point budget of one LDS accumulator: the sum of |tap| over every pair
-// of a row bounds |sample|, since the pulse never exceeds 1 in magnitude;
-// the bound plus the per-add rounding slack is mapped just below 2^31.
+// Fixed-point budget of the LDS accumulators of one work item: a bound on the
+// sum of |tap| over every pair bounds every sample, since the pulse never
+// exceeds 1 in magnitude; the bound plus the per-add rounding slack is mapped
+// just below 2^31.
 constexpr float kFixedBudget = 2147483648.0f - 262144.0f;
 constexpr float kBoundMargin = 1.0001f;
 
-// Upper bound of A = r^g / D for one pair, in FP32 (used only for the scale).
-__device__ __forceinline__ float pair_amp_bound(double px, double py, double pz, double mx, double my, double mz,
-                                                float amp) {
-    const float dx = static_cast<float>(px - mx), dy = static_cast<float>(py - my), dz = static_cast<float>(pz - mz);
-    const float d = __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
-    return amp / d;
+// Upper bound of r^g / D over the microphones of a work item for one table
+// row: D >= |pos - centre| - rho (rho = largest |mic - centre| of the group);
+// rows inside that sphere fall back to the exact nearest microphone.
+__device__ __forceinline__ float row_amp_bound(const ItemCtx& c, double px, double py, double pz, float amp,
+                                               const double* __restrict__ micq) {
+    const float ex = static_cast<float>(px - c.cx), ey = static_cast<float>(py - c.cy),
+                ez = static_cast<float>(pz - c.cz);
+    float dmin = __builtin_sqrtf(__builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez))) * 0.999999f - c.rho;
+    if (dmin < 1e-3f) {
+        dmin = 3.0e38f;
+        for (int m = 0; m < c.w.n_mic; ++m) {
+            const float dx = static_cast<float>(px - micq[3 * m]), dy = static_cast<float>(py - micq[3 * m + 1]),
+                        dz = static_cast<float>(pz - micq[3 * m + 2]);
+            dmin = fminf(dmin, __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) * 0.999999f);
+        }
+    }
+    return amp / dmin;
 }
 
 template <int NT>
@@ -369,12 +407,13 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
     extern __shared__ int acc[];
     __shared__ int list[kListCap];
     __shared__ int wave_cnt[NT / 64];
-    __shared__ float bound[NT];
-    __shared__ float row_scale[kMaxMicGroup];
+    __shared__ float bound[NT / 64];
+    __shared__ double micq[3 * kMaxMicGroup];
+    __shared__ float s_scale;
     __shared__ int s_item;
     const DescHeader* H = hdr(desc);
     const int n_items = H->n_items;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&counters[0], 1);
         __syncthreads();
@@ -385,72 +424,80 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
         const int mg = c.w.n_mic;
         const int nacc = mg * c.rowlen;
         for (int k = tid; k < nacc; k += NT) acc[k] = 0;
-        // this thread's microphone and image slot
-        const int ipp = NT / mg;
-        const int my_m = tid % mg, my_slot = tid / mg;
-        const double* mq = mic + 3 * (c.mic0_glob + my_m);
-        const double mx = mq[0], my = mq[1], mz = mq[2];
-        int* row = acc + my_m * c.rowlen;
+        if (tid < 3 * mg) micq[tid] = mic[3 * c.mic0_glob + tid];
         const int shift = kHalo - kHalf - c.w.t0;   // LDS index of tap 0 = k + shift
-        // ---- pass 1: per-row bound of the sum of |taps| (fixed thread order)
+        __syncthreads();
+        // ---- pass 1: bound of the sum of |taps| over the item (fixed order)
         float bsum = 0.0f;
         for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
             const int seg1 = min(c.n_img, seg0 + kListCap);
             int n_list = seg1 - seg0;
             if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
-            if (my_slot < ipp) {
-                for (int e = my_slot; e < n_list; e += ipp) {
-                    const int i = c.w.full ? seg0 + e : list[e];
-                    double px, py, pz, g;
-                    image_row(c, i, table, src, c.w.src, px, py, pz, g);
-                    const float amp = exp2f(static_cast<float>(g * c.log2r));
-                    bsum += pair_amp_bound(px, py, pz, mx, my, mz, amp);
-                }
+            for (int e = tid; e < n_list; e += NT) {
+                const int i = c.w.full ? seg0 + e : list[e];
+                double px, py, pz, g;
+                image_row(c, i, table, src, c.w.src, px, py, pz, g);
+                const float amp = exp2f(static_cast<float>(g * c.log2r));
+                bsum += row_amp_bound(c, px, py, pz, amp, micq);
             }
             __syncthreads();
         }
-        bound[tid] = bsum;
+        for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) bound[wave] = bsum;
         __syncthreads();
-        if (tid < mg) {
+        if (tid == 0) {
             float b = 0.0f;
-            for (int t = tid; t < ipp * mg; t += mg) b += bound[t];
+            for (int w = 0; w < NT / 64; ++w) b += bound[w];
             b *= kBoundMargin;
-            row_scale[tid] = b > 0.0f ? kFixedBudget / b : 1.0f;
+            s_scale = (b > 0.0f && b < 3.0e38f) ? kFixedBudget / b : 0.0f;
         }
         __syncthreads();
-        const float scale = row_scale[my_m];
-        // ---- pass 2: scatter the taps as rounded fixed-point integers
+        const float scale = s_scale;
+        // ---- pass 2: scatter the taps as rounded fixed-point integers.  Pair
+        // p = m * n_list + e: a wave takes consecutive images of one microphone.
         for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
             const int seg1 = min(c.n_img, seg0 + kListCap);
             int n_list = seg1 - seg0;
             if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
-            if (my_slot < ipp) {
-                for (int e = my_slot; e < n_list; e += ipp) {
-                    const int i = c.w.full ? seg0 + e : list[e];
-                    double px, py, pz, g;
-                    image_row(c, i, table, src, c.w.src, px, py, pz, g);
-                    const float amp = exp2f(static_cast<float>(g * c.log2r));
-                    const Pair P = pair_setup(px, py, pz, mx, my, mz, c.fs_over_c, amp);
-                    const int b0 = P.k + shift;
-                    if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
-                    const float aS = fabsf(P.S) * scale;
-                    const float sq = __builtin_sqrtf(aS);
-                    const float cd = sq * P.cy, sd = sq * P.sy;
-                    const float sig = P.S < 0.0f ? -1.0f : 1.0f;
-                    const float sdl = sig * P.dl;
-                    const float v0 = (P.A * scale) * P.sinc * (P.cy * P.cy);
-                    fwd_taps(std::make_integer_sequence<int, kTaps>{}, row + b0, cd, sd, sig, sdl, v0);
+            const int n_pairs = n_list * mg;
+            // (m, e) of pair p = tid + k NT, advanced without division
+            int p = tid, m = 0, e = tid;
+            while (e >= n_list && m < mg) {
+                e -= n_list;
+                ++m;
+            }
+            double px = 0.0, py = 0.0, pz = 0.0, g = 0.0;
+            if (p < n_pairs) image_row(c, c.w.full ? seg0 + e : list[e], table, src, c.w.src, px, py, pz, g);
+            while (p < n_pairs) {
+                const int cm = m;
+                const double cpx = px, cpy = py, cpz = pz, cg = g;
+                p += NT;
+                e += NT;
+                while (e >= n_list && m < mg) {
+                    e -= n_list;
+                    ++m;
                 }
+                if (p < n_pairs)   // prefetch the next pair's row
+                    image_row(c, c.w.full ? seg0 + e : list[e], table, src, c.w.src, px, py, pz, g);
+                const float amp = exp2f(static_cast<float>(cg * c.log2r));
+                const Pair P = pair_setup(cpx, cpy, cpz, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2],
+                                          c.fs_over_c, amp);
+                const int b0 = P.k + shift;
+                if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
+                const float S = P.S * scale;
+                const float v0h = __builtin_fmaf((P.A * scale) * P.sinc, P.cy * P.cy, 0.5f);
+                fwd_taps(std::make_integer_sequence<int, kTaps>{}, acc + cm * c.rowlen + b0, P.dl, S, P.cy, P.sy,
+                         v0h);
             }
             __syncthreads();
         }
         // writeback of the tile core, samples [t0, min(t0 + len, T))
         const int nvalid = min(c.w.len, c.T - c.w.t0);
+        const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
         for (int m = 0; m < mg; ++m) {
             float* dst = out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + m) * c.T +
                          c.w.t0;
             const int* srcrow = acc + m * c.rowlen + kHalo;
-            const float inv = 1.0f / row_scale[m];
             for (int n = tid; n < nvalid; n += NT) dst[n] = static_cast<float>(srcrow[n]) * inv;
         }
         __syncthreads();
@@ -732,8 +779,6 @@ extern "C" int framrir_render(const framrir_plan* plan, const void* desc_dev, co
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     int* counters = static_cast<int*>(ws_dev);
-    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, counters);
-    if ((rc = check_launch("zero_counters_kernel"))) return rc;
     return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, counters, st);
 }
 
@@ -763,8 +808,6 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
     hipStream_t st = static_cast<hipStream_t>(stream);
     int* counters = static_cast<int*>(ws_dev);
     float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + kWsCounterBytes);
-    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, counters);
-    if ((rc = check_launch("zero_counters_kernel"))) return rc;
     const int lds = plan->launch.lds_bytes;
     const dim3 grid(plan->grid), block(plan->launch.wg_threads);
     switch (plan->launch.wg_threads) {
@@ -785,6 +828,15 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
     hipLaunchKernelGGL(finalize_kernel, dim3(plan->header.n_rooms), dim3(256), 0, st, desc_dev, partials,
                        grad_mic_dev, grad_src_dev, grad_r_dev);
     return check_launch("finalize_kernel");
+}
+
+extern "C" int framrir_workspace_init(void* ws_dev, size_t ws_bytes, void* stream) {
+    if (!ws_dev || ws_bytes < static_cast<size_t>(kWsCounterBytes) || !aligned(ws_dev, 256))
+        return fr_fail(FRAMRIR_E_WORKSPACE, "workspace must be >= %lld bytes and 256-byte aligned",
+                       static_cast<long long>(kWsCounterBytes));
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       static_cast<int*>(ws_dev));
+    return check_launch("zero_counters_kernel");
 }
 
 extern "C" int framrir_philox4x32(const uint32_t* ctr_dev, const uint32_t* key_dev, uint32_t* out_dev, int64_t n,

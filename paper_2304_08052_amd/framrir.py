@@ -61,6 +61,7 @@ EXPORTS = {
     "framrir_render": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_forward": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_render_backward": (ctypes.c_int, [ctypes.c_void_p] * 11 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_workspace_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_host_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64]),
@@ -189,9 +190,10 @@ class Plan:
         return torch.empty(self.info.out_floats, dtype=torch.float32, device=self.device)
 
     def workspace(self, backward=False):
+        """Render (or backward) workspace, initialised for its first call."""
         import torch
         n = self.info.ws_bwd_bytes if backward else self.info.ws_bytes
-        return torch.empty(n, dtype=torch.uint8, device=self.device)
+        return torch.zeros(n, dtype=torch.uint8, device=self.device)
 
     # ---- device calls ------------------------------------------------------
     def draw(self, table=None, aux=False, words=False, stream=None):
