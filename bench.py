@@ -45,6 +45,9 @@ def parse_args():
     p.add_argument("--lds-bytes", type=int, default=None)
     p.add_argument("--wg-threads", type=int, default=None)
     p.add_argument("--max-mic-group", type=int, default=None)
+    p.add_argument("--waves-per-simd", type=int, default=None)
+    p.add_argument("--copy-probe-mb", type=int, default=0,
+                   help="run one plain device copy of this many MiB first (reference for HBM counters)")
     return p.parse_args()
 
 
@@ -108,6 +111,8 @@ def main():
         launch["wg_threads"] = args.wg_threads
     if args.max_mic_group:
         launch["max_mic_group"] = args.max_mic_group
+    if args.waves_per_simd:
+        launch["waves_per_simd"] = args.waves_per_simd
     t0 = time.perf_counter()
     plan = fr.Plan(batch, launch=launch)
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -123,6 +128,12 @@ def main():
     ws_b = plan.workspace(backward=True)
     grad = torch.from_numpy(W.upstream_grad(info.out_floats)).cuda()
     stream = torch.cuda.current_stream()
+    if args.copy_probe_mb > 0:   # known traffic: N MiB read + N MiB written
+        a = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def fwd_step(ev=None):
         plan.draw(table)

@@ -93,17 +93,21 @@ typedef struct framrir_params {
 } framrir_params;
 
 /* Launch shape of the render and backward kernels (not part of the method):
- * lds_bytes  LDS accumulator budget per workgroup (4096 .. 160000),
- * wg_threads threads per workgroup (64 .. 1024, multiple of 64),
- * grid_wgs   workgroups of the persistent render grid (0 = one per work item
- *            up to 256 * floor(160000 / lds_bytes)).
+ * lds_bytes      LDS accumulator budget per workgroup, a multiple of 16 in
+ *                [4096, 143616] and >= 28 * wg_threads,
+ * wg_threads     threads per workgroup: 256, 512 or 1024,
+ * grid_wgs       workgroups of the persistent grid (0 = as many as fit on
+ *                256 compute units at once, capped at the number of items),
+ * max_mic_group  microphones per work item, 1 .. 16 (0 = 8),
+ * waves_per_simd register budget: 4 or 8 resident waves per SIMD (0 = 4).
  * A time tile holds tile_len = floor(lds_bytes / 4 / m_group) - 160 samples
- * of m_group microphones. */
+ * of m_group microphones; rooms whose RIR is longer are split in time. */
 typedef struct framrir_launch {
     int32_t lds_bytes;
     int32_t wg_threads;
     int32_t grid_wgs;
-    int32_t max_mic_group; /* microphones per work item, 1 .. 16 (0 = 8) */
+    int32_t max_mic_group;
+    int32_t waves_per_simd;
 } framrir_launch;
 
 /* Sizes of a plan. */
@@ -126,7 +130,7 @@ typedef struct framrir_plan framrir_plan; /* opaque, host memory */
 /* Plans a batch (host only; Sec. II, III-A, III-C, Eq. 2, 5).
  * rooms[n_rooms]; src: [sum n_src, 3] FP64 host; mic: [sum n_mic, 3] FP64
  * host.  prm and launch may be NULL for the defaults (alpha 0.25, beta 1,
- * a -2, b 2, tau 0.25, I in [1024, 4096]; lds 131072 B, 256 threads).
+ * a -2, b 2, tau 0.25, I in [1024, 4096]; lds 131072 B, 1024 threads).
  * Per room: T = ceil(T60 fs); R = V / S; r from Eq. 2 unless overridden;
  * centre = mean microphone.  Per source: d0 = |src - centre|,
  * RR_max = max(1, (log10 c0T60 - log10 d0 - 3) / log10 r), and

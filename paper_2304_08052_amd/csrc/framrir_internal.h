@@ -20,7 +20,7 @@ namespace framrir {
 constexpr int kTaps = 81;
 constexpr int kHalf = 40;          // taps are k - 40 .. k + 40 around k = floor(t + 1/2)
 constexpr int kHalo = 80;          // LDS guard samples on each side of a time tile
-constexpr int kListCap = 4096;     // compacted image indices per pass of a tile
+constexpr int kListCap = 4096;     // largest number of image indices compacted per pass of a tile
 constexpr int kMaxMicGroup = 16;   // microphones per work item
 constexpr int kPartialStride = 3 * kMaxMicGroup + 4;   // backward partials per item
 

@@ -140,32 +140,49 @@ struct Pair {
     float ux, uy, uz, D;
 };
 
+// sinc(x) = sin(pi x) / (pi x) for |x| <= 1/2 from its Taylor series in
+// z = (pi x)^2 (terms to z^6; the first omitted term is below 5e-10).
+__device__ __forceinline__ float sinc_small(float x) {
+    const float px = kPiF * x;
+    const float z = px * px;
+    float acc = 1.0f / 6227020800.0f;                   // 1/13!
+    acc = __builtin_fmaf(acc, z, -1.0f / 39916800.0f);  // 1/11!
+    acc = __builtin_fmaf(acc, z, 1.0f / 362880.0f);     // 1/9!
+    acc = __builtin_fmaf(acc, z, -1.0f / 5040.0f);      // 1/7!
+    acc = __builtin_fmaf(acc, z, 1.0f / 120.0f);        // 1/5!
+    acc = __builtin_fmaf(acc, z, -1.0f / 6.0f);         // 1/3!
+    return __builtin_fmaf(acc, z, 1.0f);
+}
+
+// Per-pair setup: D = |pos - mic| and t = D fs / c in FP64 (delays up to
+// ~6e4 samples must stay accurate to ~1e-7 samples), then FP32 quantities.
 __device__ __forceinline__ Pair pair_setup(double px, double py, double pz, double mx, double my, double mz,
                                            double fs_over_c, float amp) {
     Pair P;
     const double dx = px - mx, dy = py - my, dz = pz - mz;
     const double d2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-    const double D = __builtin_sqrt(d2);
+    // sqrt from the hardware reciprocal square root and one Newton step
+    const double rs = __builtin_amdgcn_rsq(d2);
+    const double y0 = d2 * rs;
+    const double D = __builtin_fma(__builtin_fma(-y0, y0, d2), 0.5 * rs, y0);
     const double t = D * fs_over_c;
     const double kf = __builtin_floor(t + 0.5);
     P.k = static_cast<int>(kf);
     P.dl = static_cast<float>(t - kf);
     const float Df = static_cast<float>(D);
-    const float invD = 1.0f / Df;
+    const float invD = __builtin_amdgcn_rcpf(Df);
     P.A = amp * invD;
     P.D = Df;
-    const double invDd = 1.0 / D;
-    P.ux = static_cast<float>(dx * invDd);
-    P.uy = static_cast<float>(dy * invDd);
-    P.uz = static_cast<float>(dz * invDd);
-    const float sp = sinpif(P.dl);
-    P.S = P.A * sp * kInvPiF;
+    P.ux = static_cast<float>(dx) * invD;
+    P.uy = static_cast<float>(dy) * invD;
+    P.uz = static_cast<float>(dz) * invD;
+    P.sinc = sinc_small(P.dl);
+    P.S = (P.A * P.dl) * P.sinc;                       // A sin(pi dl) / pi
     const float y = (kPiF / 81.0f) * P.dl;
     const float y2 = y * y;
     // |y| <= pi / 162: three Taylor terms are exact to FP32 rounding
     P.cy = __builtin_fmaf(y2, __builtin_fmaf(y2, 1.0f / 24.0f, -0.5f), 1.0f);
     P.sy = y * __builtin_fmaf(y2, __builtin_fmaf(y2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
-    P.sinc = (P.dl == 0.0f) ? 1.0f : sp / (kPiF * P.dl);
     return P;
 }
 
@@ -225,9 +242,23 @@ __device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, int* 
     (fwd_tap<J>(row, dl, S, cy, sy, v0), ...);
 }
 
-// ---- backward taps: s0 += G A P(x), s1 += G A P'(x) with
+// ---- backward taps: s0 += G A P(x), s1 += G A P'(x), x = m - dl.  With
+// v(dl) = A P(m - dl) = S Q_m(dl) and dS/ddl = A cos(pi dl) = Ac,
+//   A P'(m - dl) = -dv/ddl = -(Ac Q_m + S Q_m').
+// Q_m' comes from the derivative of the same polynomial; the taps next to the
+// centre use the closed form
 //   A P'(x) = (1/x) [(-1)^m (A cos(pi dl) w + (2 pi/81) S sw cw) - A P(x)],
 //   w = cw^2, cw = cos(pi x/81), sw = sin(pi x/81).
+template <int J, int K>
+__device__ __forceinline__ float tap_horner_deriv(float dl) {
+    constexpr float c = static_cast<float>((K + 1) * static_cast<double>(kPolyCoef[J][K + 1]));
+    if constexpr (K + 1 == kPolyDeg[J]) {
+        return c;
+    } else {
+        return __builtin_fmaf(tap_horner_deriv<J, K + 1>(dl), dl, c);
+    }
+}
+
 template <int J>
 __device__ __forceinline__ void bwd_tap(const float* __restrict__ row, float cy, float sy, float dl, float S,
                                         float Ac, float S2, float v0, float dp0, float& s0, float& s1) {
@@ -236,7 +267,7 @@ __device__ __forceinline__ void bwd_tap(const float* __restrict__ row, float cy,
     if constexpr (m == 0) {
         s0 = __builtin_fmaf(G, v0, s0);
         s1 = __builtin_fmaf(G, dp0, s1);
-    } else {
+    } else if constexpr (kPolyDeg[J] < 0) {
         constexpr float M = static_cast<float>(m);
         constexpr float C = static_cast<float>(ct_cos(kPiOver81 * m));
         constexpr float Sn = static_cast<float>(ct_sin(kPiOver81 * m));
@@ -250,6 +281,11 @@ __device__ __forceinline__ void bwd_tap(const float* __restrict__ row, float cy,
         const float dp = rx * __builtin_fmaf(sgn, inner, -val);
         s0 = __builtin_fmaf(G, val, s0);
         s1 = __builtin_fmaf(G, dp, s1);
+    } else {
+        const float q = tap_horner<J, 0>(dl);
+        const float dq = tap_horner_deriv<J, 0>(dl);
+        s0 = __builtin_fmaf(G, S * q, s0);
+        s1 = __builtin_fmaf(-G, __builtin_fmaf(Ac, q, S * dq), s1);
     }
 }
 
@@ -258,6 +294,21 @@ __device__ __forceinline__ void bwd_taps(std::integer_sequence<int, J...>, const
                                          float sy, float dl, float S, float Ac, float S2, float v0, float dp0,
                                          float& s0, float& s1) {
     (bwd_tap<J>(row, cy, sy, dl, S, Ac, S2, v0, dp0, s0, s1), ...);
+}
+
+// cos(pi x) for |x| <= 1/2 from its Taylor series in z = (pi x)^2 (to z^8).
+__device__ __forceinline__ float cospi_small(float x) {
+    const float px = kPiF * x;
+    const float z = px * px;
+    float acc = 1.0f / 20922789888000.0f;                // 1/16!
+    acc = __builtin_fmaf(acc, z, -1.0f / 87178291200.0f); // 1/14!
+    acc = __builtin_fmaf(acc, z, 1.0f / 479001600.0f);    // 1/12!
+    acc = __builtin_fmaf(acc, z, -1.0f / 3628800.0f);     // 1/10!
+    acc = __builtin_fmaf(acc, z, 1.0f / 40320.0f);        // 1/8!
+    acc = __builtin_fmaf(acc, z, -1.0f / 720.0f);         // 1/6!
+    acc = __builtin_fmaf(acc, z, 1.0f / 24.0f);           // 1/4!
+    acc = __builtin_fmaf(acc, z, -0.5f);                  // 1/2!
+    return __builtin_fmaf(acc, z, 1.0f);
 }
 
 // sinc'(x) for |x| <= 1/2 from its Taylor series (no cancellation near 0):
@@ -399,13 +450,13 @@ __device__ __forceinline__ float row_amp_bound(const ItemCtx& c, double px, doub
     return amp / dmin;
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ desc, const double* __restrict__ table,
-                                                     const double* __restrict__ mic, const double* __restrict__ src,
-                                                     const double* __restrict__ r_in, float* __restrict__ out,
-                                                     int* __restrict__ counters) {
+template <int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
+render_kernel(const void* __restrict__ desc, const double* __restrict__ table, const double* __restrict__ mic,
+              const double* __restrict__ src, const double* __restrict__ r_in, float* __restrict__ out,
+              int* __restrict__ counters, int acc_words, int list_cap) {
     extern __shared__ int acc[];
-    __shared__ int list[kListCap];
+    int* list = acc + acc_words;
     __shared__ int wave_cnt[NT / 64];
     __shared__ float bound[NT / 64];
     __shared__ double micq[3 * kMaxMicGroup];
@@ -421,6 +472,7 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
         if (item >= n_items) break;
         ItemCtx c;
         load_item(desc, item, mic, r_in, c);
+        const int seg_cap = c.w.full ? c.n_img : list_cap;   // images compacted per pass of a tile
         const int mg = c.w.n_mic;
         const int nacc = mg * c.rowlen;
         for (int k = tid; k < nacc; k += NT) acc[k] = 0;
@@ -429,8 +481,8 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
         __syncthreads();
         // ---- pass 1: bound of the sum of |taps| over the item (fixed order)
         float bsum = 0.0f;
-        for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
-            const int seg1 = min(c.n_img, seg0 + kListCap);
+        for (int seg0 = 0; seg0 < c.n_img; seg0 += seg_cap) {
+            const int seg1 = min(c.n_img, seg0 + seg_cap);
             int n_list = seg1 - seg0;
             if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
             for (int e = tid; e < n_list; e += NT) {
@@ -455,8 +507,8 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
         const float scale = s_scale;
         // ---- pass 2: scatter the taps as rounded fixed-point integers.  Pair
         // p = m * n_list + e: a wave takes consecutive images of one microphone.
-        for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
-            const int seg1 = min(c.n_img, seg0 + kListCap);
+        for (int seg0 = 0; seg0 < c.n_img; seg0 += seg_cap) {
+            const int seg1 = min(c.n_img, seg0 + seg_cap);
             int n_list = seg1 - seg0;
             if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
             const int n_pairs = n_list * mg;
@@ -516,16 +568,13 @@ __global__ void __launch_bounds__(NT) render_kernel(const void* __restrict__ des
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
-template <int NT>
-__global__ void __launch_bounds__(NT) backward_kernel(const void* __restrict__ desc,
-                                                       const double* __restrict__ table,
-                                                       const double* __restrict__ mic,
-                                                       const double* __restrict__ src,
-                                                       const double* __restrict__ r_in,
-                                                       const float* __restrict__ gout,
-                                                       float* __restrict__ partials, int* __restrict__ counters) {
+template <int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
+backward_kernel(const void* __restrict__ desc, const double* __restrict__ table, const double* __restrict__ mic,
+                const double* __restrict__ src, const double* __restrict__ r_in, const float* __restrict__ gout,
+                float* __restrict__ partials, int* __restrict__ counters, int acc_words, int list_cap) {
     extern __shared__ float tile[];
-    __shared__ int list[kListCap];
+    int* list = reinterpret_cast<int*>(tile) + acc_words;
     __shared__ int wave_cnt[NT / 64];
     __shared__ int s_item;
     const DescHeader* H = hdr(desc);
@@ -538,6 +587,7 @@ __global__ void __launch_bounds__(NT) backward_kernel(const void* __restrict__ d
         if (item >= n_items) break;
         ItemCtx c;
         load_item(desc, item, mic, r_in, c);
+        const int seg_cap = c.w.full ? c.n_img : list_cap;
         const int mg = c.w.n_mic;
         // dL/dh of the tile core; zero in the halo and beyond T, so that each
         // pair counts only the taps of this tile
@@ -560,8 +610,8 @@ __global__ void __launch_bounds__(NT) backward_kernel(const void* __restrict__ d
         const float inv_r = static_cast<float>(1.0 / c.r);
         float gmx = 0.f, gmy = 0.f, gmz = 0.f, gsx = 0.f, gsy = 0.f, gsz = 0.f, gr = 0.f;
         __syncthreads();
-        for (int seg0 = 0; seg0 < c.n_img; seg0 += kListCap) {
-            const int seg1 = min(c.n_img, seg0 + kListCap);
+        for (int seg0 = 0; seg0 < c.n_img; seg0 += seg_cap) {
+            const int seg1 = min(c.n_img, seg0 + seg_cap);
             int n_list = seg1 - seg0;
             if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
             if (my_slot < ipp) {
@@ -573,7 +623,7 @@ __global__ void __launch_bounds__(NT) backward_kernel(const void* __restrict__ d
                     const Pair P = pair_setup(px, py, pz, mx, my, mz, c.fs_over_c, amp);
                     const int b0 = P.k + shift;
                     if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
-                    const float cpd = cospif(P.dl);
+                    const float cpd = cospi_small(P.dl);
                     const float Ac = P.A * cpd;
                     const float S2 = (2.0f * kPiF / 81.0f) * P.S;
                     const float v0 = P.A * P.sinc * (P.cy * P.cy);
@@ -728,7 +778,7 @@ template <typename F>
 int allow_lds(F kernel) {
     static int status = [&] {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxAccLdsBytes);
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLdsBytes);
         return e == hipSuccess ? 0 : static_cast<int>(e);
     }();
     if (status != 0)
@@ -738,22 +788,22 @@ int allow_lds(F kernel) {
 
 int launch_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev, const double* mic_dev,
                   const double* src_dev, const double* r_dev, float* out_dev, int* counters, hipStream_t st) {
-    const int lds = plan->launch.lds_bytes;
+    const int lds = plan->launch.lds_bytes + 4 * plan->list_cap;
+    const int acc_words = plan->launch.lds_bytes / 4;
     const dim3 grid(plan->grid), block(plan->launch.wg_threads);
-    switch (plan->launch.wg_threads) {
-#define FR_CASE(NT)                                                                                         \
-    case NT:                                                                                                \
-        if (int rc = allow_lds(render_kernel<NT>)) return rc;                                                  \
-        hipLaunchKernelGGL(render_kernel<NT>, grid, block, lds, st, desc_dev, table_dev, mic_dev, src_dev, \
-                           r_dev, out_dev, counters);                                                       \
+    const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
+    switch (key) {
+#define FR_CASE(NT, WPE)                                                                                    \
+    case NT * 16 + WPE:                                                                                     \
+        if (int rc = allow_lds(render_kernel<NT, WPE>)) return rc;                                          \
+        hipLaunchKernelGGL((render_kernel<NT, WPE>), grid, block, lds, st, desc_dev, table_dev, mic_dev,   \
+                           src_dev, r_dev, out_dev, counters, acc_words, plan->list_cap);                   \
         break;
-        FR_CASE(256)
-        FR_CASE(512)
-        FR_CASE(1024)
+        FR_KERNEL_SHAPES(FR_CASE)
 #undef FR_CASE
         default:
-            return fr_fail(FRAMRIR_E_UNSUPPORTED, "wg_threads %d not compiled (256, 512, 1024)",
-                           plan->launch.wg_threads);
+            return fr_fail(FRAMRIR_E_UNSUPPORTED, "launch shape %d threads x %d waves/SIMD not compiled",
+                           plan->launch.wg_threads, plan->launch.waves_per_simd);
     }
     return check_launch("render_kernel");
 }
@@ -808,21 +858,21 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
     hipStream_t st = static_cast<hipStream_t>(stream);
     int* counters = static_cast<int*>(ws_dev);
     float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + kWsCounterBytes);
-    const int lds = plan->launch.lds_bytes;
+    const int lds = plan->launch.lds_bytes + 4 * plan->list_cap;
+    const int acc_words = plan->launch.lds_bytes / 4;
     const dim3 grid(plan->grid), block(plan->launch.wg_threads);
-    switch (plan->launch.wg_threads) {
-#define FR_CASE(NT)                                                                                           \
-    case NT:                                                                                                  \
-        if (int rc2 = allow_lds(backward_kernel<NT>)) return rc2;                                              \
-        hipLaunchKernelGGL(backward_kernel<NT>, grid, block, lds, st, desc_dev, table_dev, mic_dev, src_dev, \
-                           r_dev, grad_out_dev, partials, counters);                                          \
+    const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
+    switch (key) {
+#define FR_CASE(NT, WPE)                                                                                     \
+    case NT * 16 + WPE:                                                                                      \
+        if (int rc2 = allow_lds(backward_kernel<NT, WPE>)) return rc2;                                       \
+        hipLaunchKernelGGL((backward_kernel<NT, WPE>), grid, block, lds, st, desc_dev, table_dev, mic_dev,  \
+                           src_dev, r_dev, grad_out_dev, partials, counters, acc_words, plan->list_cap);     \
         break;
-        FR_CASE(256)
-        FR_CASE(512)
-        FR_CASE(1024)
+        FR_KERNEL_SHAPES(FR_CASE)
 #undef FR_CASE
         default:
-            return fr_fail(FRAMRIR_E_UNSUPPORTED, "wg_threads %d not compiled", plan->launch.wg_threads);
+            return fr_fail(FRAMRIR_E_UNSUPPORTED, "launch shape not compiled");
     }
     if ((rc = check_launch("backward_kernel"))) return rc;
     hipLaunchKernelGGL(finalize_kernel, dim3(plan->header.n_rooms), dim3(256), 0, st, desc_dev, partials,

@@ -102,8 +102,9 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     } else {
         prm = framrir_params{0.25, 1.0, -2.0, 2.0, 0.25, 1024, 4096, FRAMRIR_TAPS, 0u};
     }
-    framrir_launch launch = launch_in ? *launch_in : framrir_launch{131072, 1024, 0, 8};
+    framrir_launch launch = launch_in ? *launch_in : framrir_launch{131072, 1024, 0, 8, 4};
     if (launch.max_mic_group == 0) launch.max_mic_group = 8;
+    if (launch.waves_per_simd == 0) launch.waves_per_simd = 4;
 
     // ---- method parameters
     if (!(std::isfinite(prm.alpha) && std::isfinite(prm.beta) && std::isfinite(prm.a) && std::isfinite(prm.b) &&
@@ -126,9 +127,13 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     if (launch.wg_threads < 64 || launch.wg_threads > 1024 || launch.wg_threads % 64 != 0)
         return fr_fail(FRAMRIR_E_RANGE, "wg_threads must be a multiple of 64 in [64, 1024] (got %d)",
                        launch.wg_threads);
-    if (launch.lds_bytes < 4096 || launch.lds_bytes > kMaxAccLdsBytes)
-        return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be in [4096, %d] (got %d)", kMaxAccLdsBytes,
-                       launch.lds_bytes);
+    if (launch.lds_bytes < 4096 || launch.lds_bytes > kMaxDynLdsBytes - 4 * kListCap || launch.lds_bytes % 16 != 0)
+        return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be a multiple of 16 in [4096, %d] (got %d)",
+                       kMaxDynLdsBytes - 4 * kListCap, launch.lds_bytes);
+    if (launch.waves_per_simd != 4 && launch.waves_per_simd != 8)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "waves_per_simd must be 4 or 8 (got %d)", launch.waves_per_simd);
+    if (launch.wg_threads != 256 && launch.wg_threads != 512 && launch.wg_threads != 1024)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "wg_threads must be 256, 512 or 1024 (got %d)", launch.wg_threads);
     if (launch.lds_bytes < 28 * launch.wg_threads)
         return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be >= 28 * wg_threads (backward reduction)");
     if (launch.max_mic_group < 1 || launch.max_mic_group > kMaxMicGroup)
@@ -370,10 +375,16 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     // ---- workspace
     plan->ws_bytes = kWsCounterBytes;
     plan->ws_bwd_bytes = kWsCounterBytes + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
+    // compaction list only for time-tiled items
+    bool tiled = false;
+    for (const WorkItem& w : it) tiled = tiled || !w.full;
+    plan->list_cap = tiled ? std::min(kListCap, max_img) : 0;
     int32_t grid = launch.grid_wgs;
     if (grid == 0) {
-        const int per_cu = std::max(1, kMaxAccLdsBytes / launch.lds_bytes);
-        grid = std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu);
+        const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + 4 * plan->list_cap + kStaticLdsBytes);
+        const int per_cu_waves = launch.waves_per_simd * 4 / (launch.wg_threads / 64);
+        const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
+        grid = static_cast<int32_t>(std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu));
     }
     plan->grid = std::max(1, grid);
     *out = plan;

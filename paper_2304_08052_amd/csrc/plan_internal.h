@@ -7,9 +7,16 @@
 #include "../../include/framrir.h"
 #include "framrir_internal.h"
 
-// Largest LDS accumulator budget per workgroup: 160 000 B of gfx950 LDS minus
-// the compacted image list, the bound reduction and small scratch.
-constexpr int kMaxAccLdsBytes = 160000 - 4 * framrir::kListCap - 6144;
+// gfx950 LDS per compute unit, and the largest dynamic LDS of one workgroup
+// (accumulator tile plus compacted image list), leaving room for the kernels'
+// static scratch.
+constexpr int kLdsPerCu = 163840;
+constexpr int kMaxDynLdsBytes = 160000;
+constexpr int kStaticLdsBytes = 2048;
+
+// Compiled (threads per workgroup, waves per SIMD) shapes of the render and
+// backward kernels.
+#define FR_KERNEL_SHAPES(X) X(256, 4) X(256, 8) X(512, 4) X(512, 8) X(1024, 4) X(1024, 8)
 // Workspace header: work-queue and completion counters of the persistent grid.
 constexpr int64_t kWsCounterBytes = 256;
 
@@ -25,6 +32,7 @@ struct framrir_plan {
     int64_t ws_bytes = 0;
     int64_t ws_bwd_bytes = 0;
     int32_t grid = 1;
+    int32_t list_cap = 0;   // compacted image indices per tile pass (0: every item covers its whole RIR)
 };
 
 int fr_fail(int code, const char* fmt, ...);

@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("lds_bytes", ctypes.c_int32), ("wg_threads", ctypes.c_int32), ("grid_wgs", ctypes.c_int32),
-                ("max_mic_group", ctypes.c_int32)]
+                ("max_mic_group", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -47,7 +47,7 @@ class PlanInfo(ctypes.Structure):
 
 
 DEFAULT_PARAMS = dict(alpha=0.25, beta=1.0, a=-2.0, b=2.0, tau=0.25, img_lo=1024, img_hi=4096)
-DEFAULT_LAUNCH = dict(lds_bytes=131072, wg_threads=1024, grid_wgs=0, max_mic_group=8)
+DEFAULT_LAUNCH = dict(lds_bytes=131072, wg_threads=1024, grid_wgs=0, max_mic_group=8, waves_per_simd=4)
 
 EXPORTS = {
     "framrir_plan_create": (ctypes.c_int, [ctypes.POINTER(Room), ctypes.c_int32, ctypes.POINTER(Params),
@@ -143,7 +143,8 @@ class Plan:
         self.mic = np.ascontiguousarray(batch["mic"], dtype=np.float64)
         p = Params(prm["alpha"], prm["beta"], prm["a"], prm["b"], prm["tau"], prm["img_lo"], prm["img_hi"],
                    FRAMRIR_TAPS, 0)
-        la = Launch(lau["lds_bytes"], lau["wg_threads"], lau["grid_wgs"], lau["max_mic_group"])
+        la = Launch(lau["lds_bytes"], lau["wg_threads"], lau["grid_wgs"], lau["max_mic_group"],
+                    lau["waves_per_simd"])
         handle = ctypes.c_void_p()
         _check(L.framrir_plan_create(rooms, n, ctypes.byref(p), ctypes.byref(la), _np_ptr(self.src),
                                      _np_ptr(self.mic), ctypes.byref(handle)))
