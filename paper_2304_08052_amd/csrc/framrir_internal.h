@@ -226,22 +226,54 @@ FR_HD void decompose(double x, uint64_t* M, int* e) {
     *e = static_cast<int>((u >> 52) & 0x7FF) - 1075;
 }
 
+// Reciprocal accurate to about one ulp (device: hardware estimate plus one
+// Newton step; host: division).  Only used where the exact checks below
+// absorb its error.
+FR_HD double approx_rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma_d(fma_d(-x, r, 1.0), r, r);
+    return r;
+#else
+    return 1.0 / x;
+#endif
+}
+
+// Exact-ish residual m - y^3 from error-free products: y^2 = p_hi + p_lo and
+// p_hi y = c_hi + c_lo exactly; m - c_hi is exact (Sterbenz), so only the
+// tiny term p_lo y is rounded.
+FR_HD double cube_residual(double m, double y) {
+    const double p_hi = y * y;
+    const double p_lo = fma_d(y, y, -p_hi);
+    const double c_hi = p_hi * y;
+    const double c_lo = fma_d(p_hi, y, -c_hi);
+    return ((m - c_hi) - c_lo) - p_lo * y;
+}
+
 // Correctly rounded cube root of a positive normal double (the inverse CDF of
-// Eq. 3).  A float seed refined by two FP64 Newton steps lands within an ulp;
-// exact midpoint comparisons then pick the nearest double.
+// Eq. 3).  The argument is scaled into m in [1, 8) by a multiple of 3 in the
+// exponent; a float seed, one Newton step and one step from the exact
+// residual give y within about half an ulp of cbrt(m).  The residual then
+// proves y is the nearest double unless cbrt(m) lies within 1e-6 ulp of a
+// rounding midpoint; those rare cases are settled by exact 256-bit integer
+// comparisons against the cubes of the midpoints.
 FR_HD double cbrt_rn(double a) {
     uint64_t A;
     int ea;
     decompose(a, &A, &ea);
-    // scale a into [1, 8) by a multiple of 3 in the exponent
     const int eb = ea + 52;                            // a = (A / 2^52) 2^eb, A/2^52 in [1, 2)
     int q3 = eb >= 0 ? eb / 3 : -((-eb + 2) / 3);      // floor(eb / 3)
     const double m = bitsd((dbits(a) & ~(uint64_t(0x7FF) << 52)) |
                            (uint64_t(1023 + (eb - 3 * q3)) << 52));   // in [1, 8)
     double y = static_cast<double>(cbrtf(static_cast<float>(m)));
-    y = y - (y * y * y - m) / (3.0 * y * y);
-    y = y - (y * y * y - m) / (3.0 * y * y);
-    y = y * bitsd(uint64_t(1023 + q3) << 52);          // exact power-of-two scaling
+    y = y - (y * y * y - m) * approx_rcp(3.0 * y * y);                 // ~1e-14
+    const double inv3y2 = approx_rcp(3.0 * y * y);
+    y = y + cube_residual(m, y) * inv3y2;                              // ~0.5 ulp
+    // offset of cbrt(m) from y in ulps of y (y in [1, 2): ulp = 2^-52)
+    const double t = cube_residual(m, y) * approx_rcp(3.0 * y * y) * 4503599627370496.0;
+    const double pow2 = bitsd(uint64_t(1023 + q3) << 52);               // exact scaling
+    if (t > -0.499999 && t < 0.499999 && y >= 1.0 && y < 2.0) return y * pow2;
+    y = y * pow2;
 #pragma unroll 1
     for (int it = 0; it < 6; ++it) {
         uint64_t Y;
@@ -260,6 +292,43 @@ FR_HD double cbrt_rn(double a) {
         break;
     }
     return y;
+}
+
+// sin(pi x) and cos(pi x) for |x| <= 2 where x is exact: x = n/2 + r with
+// |r| <= 1/4 exactly, then Taylor series of sin and cos at pi r (|pi r| <=
+// pi/4; terms to degree 17/18, remainder below 1e-19) and a quarter-turn
+// rotation by n.
+FR_HD void sincospi_d(double x, double* s_out, double* c_out) {
+    const double n = __builtin_rint(2.0 * x);
+    const double r = x - 0.5 * n;                      // exact
+    const double z = r * 3.141592653589793238;
+    const double z2 = z * z;
+    double ps = 2.8114572543455206e-15;                // 1/17!
+    ps = fma_d(ps, -z2, 7.647163731819816e-13);        // 1/15!
+    ps = fma_d(ps, -z2, 1.6059043836821613e-10);       // 1/13!
+    ps = fma_d(ps, -z2, 2.505210838544172e-08);        // 1/11!
+    ps = fma_d(ps, -z2, 2.7557319223985893e-06);       // 1/9!
+    ps = fma_d(ps, -z2, 1.984126984126984e-04);        // 1/7!
+    ps = fma_d(ps, -z2, 8.333333333333333e-03);        // 1/5!
+    ps = fma_d(ps, -z2, 1.6666666666666666e-01);       // 1/3!
+    ps = fma_d(ps, -z2, 1.0);
+    const double sr = z * ps;
+    double pc = 1.5619206968586225e-16;                // 1/18!
+    pc = fma_d(pc, -z2, 4.779477332387385e-14);        // 1/16!
+    pc = fma_d(pc, -z2, 1.1470745597729725e-11);       // 1/14!
+    pc = fma_d(pc, -z2, 2.08767569878681e-09);         // 1/12!
+    pc = fma_d(pc, -z2, 2.755731922398589e-07);        // 1/10!
+    pc = fma_d(pc, -z2, 2.48015873015873e-05);         // 1/8!
+    pc = fma_d(pc, -z2, 1.388888888888889e-03);        // 1/6!
+    pc = fma_d(pc, -z2, 4.1666666666666664e-02);       // 1/4!
+    pc = fma_d(pc, -z2, 0.5);                          // 1/2!
+    const double cr = fma_d(pc, -z2, 1.0);
+    const int q = static_cast<int>(n) & 3;
+    // sin(pi r + q pi/2), cos(pi r + q pi/2)
+    const double s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+    const double c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
+    *s_out = s;
+    *c_out = c;
 }
 
 }  // namespace framrir

@@ -105,9 +105,11 @@ __global__ void __launch_bounds__(256) draw_kernel(const void* __restrict__ desc
     else drt = dr;
     g = g + p * drt;
     g = fmin(fmax(g, 1.0), S->rrmax);
+    // cos and sin of theta = 2 pi u0 and phi = pi (u1 - 1/2) from the exact
+    // arguments 2 u0 and u1 - 1/2
     double st, ctheta, sp, cp;
-    sincos(theta, &st, &ctheta);
-    sincos(phi, &sp, &cp);
+    sincospi_d(2.0 * u0, &st, &ctheta);
+    sincospi_d(u1 - 0.5, &sp, &cp);
     out[0] = R->centre[0] + dist * (cp * ctheta);
     out[1] = R->centre[1] + dist * (cp * st);
     out[2] = R->centre[2] + dist * sp;

@@ -159,3 +159,25 @@ def test_work_items_cover_every_output_once():
                     pos += ln
                 assert pos >= plan.T[b] and pos - tiles[-1][1] < plan.T[b]
             s_glob += 1
+
+
+def near_midpoint_cubes(n, seed=0):
+    """Doubles a whose cube root lies very close to a rounding midpoint:
+    a = RN(((y + y_next)/2)^3) for random 53-bit y in [1, 2), plus its
+    neighbours -- the cases a correctly rounded cube root must settle
+    exactly."""
+    from fractions import Fraction
+    rng = np.random.default_rng(seed)
+    out = []
+    for y in rng.uniform(1.0, 2.0, n):
+        mid = (Fraction(float(y)) + Fraction(np.nextafter(y, 3.0))) / 2
+        a = float(mid ** 3)
+        out += [a, np.nextafter(a, 0.0), np.nextafter(a, 9.0)]
+    return np.array(out)
+
+
+def test_host_cbrt_near_midpoints():
+    x = near_midpoint_cubes(3000)
+    got = fr.host_cbrt_rn(x)
+    want = np.array([oracle_cbrt(float(v)) for v in x])
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))

@@ -81,8 +81,9 @@ def test_cbrt_bit_exact():
     say("cbrt 2e5 arguments")
     rng = np.random.default_rng(11)
     u = (rng.integers(0, 2**32, 150000).astype(np.float64) + 0.5) * 2.0**-32
+    from tests.test_abi_host import near_midpoint_cubes
     x = np.concatenate([1.0 / 64.0 + u * (63.0 / 64.0), u[:20000], 10.0 ** rng.uniform(-300, 300, 30000),
-                        np.array([1.0, 8.0, 27.0, 0.125, 2.0, 3.0])])
+                        np.array([1.0, 8.0, 27.0, 0.125, 2.0, 3.0]), near_midpoint_cubes(2000, seed=5)])
     y = fr.cbrt_rn(torch.from_numpy(x).cuda()).cpu().numpy()
     want = np.array([oracle_cbrt(float(v)) for v in x])
     assert np.array_equal(y.view(np.uint64), want.view(np.uint64))
