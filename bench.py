@@ -46,6 +46,9 @@ def parse_args():
     p.add_argument("--wg-threads", type=int, default=None)
     p.add_argument("--max-mic-group", type=int, default=None)
     p.add_argument("--waves-per-simd", type=int, default=None)
+    p.add_argument("--tune", action="store_true", help="pick the launch shape with the autotuner first")
+    p.add_argument("--per-room", action="store_true",
+                   help="also time the plain per-room launch path on the same batch")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="run one plain device copy of this many MiB first (reference for HBM counters)")
     return p.parse_args()
@@ -113,6 +116,14 @@ def main():
         launch["max_mic_group"] = args.max_mic_group
     if args.waves_per_simd:
         launch["waves_per_simd"] = args.waves_per_simd
+    if args.workload == "mixed":
+        return run_mixed(args, batch, desc, launch)
+    tuned = None
+    if args.tune:
+        from paper_2304_08052_amd import autotune
+        best, results = autotune.tune(batch, store=False)
+        launch = dict(best, **launch)
+        tuned = [dict(ms=round(ms, 4), **{k: v for k, v in l.items() if k != "grid_wgs"}) for ms, l in results[:5]]
     t0 = time.perf_counter()
     plan = fr.Plan(batch, launch=launch)
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -203,6 +214,25 @@ def main():
         torch.cuda.synchronize()
         fb_ms = t_start.elapsed_time(t_end) / args.steps
 
+    per_room_ms = None
+    if args.per_room:
+        pr = fr.PerRoom(batch, launch=launch)
+        pr_out = torch.empty_like(out)
+        for _ in range(max(1, args.warmup // 2)):
+            pr.forward(pr_out)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // 10)
+        t_start.record(stream)
+        for _ in range(reps):
+            pr.forward(pr_out)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        per_room_ms = t_start.elapsed_time(t_end) / reps
+        fwd_step()
+        torch.cuda.synchronize()
+        if not torch.equal(pr_out, out):
+            raise RuntimeError("per-room path disagrees with the batched path")
+
     step_ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
     value = n_rirs / (step_ms * 1e-3)
     achieved = taps * FLOPS_PER_TAP / (render_ms * 1e-3) / 1e12
@@ -252,7 +282,61 @@ def main():
         "graph_ms_per_step": graph_ms,
         "fwd_bwd_ms_per_step": fb_ms,
         "fwd_bwd_over_fwd": (fb_ms / eager_ms) if fb_ms else None,
+        "per_room_ms_per_step": per_room_ms,
         "plan_host_ms": plan_ms,
+        "autotune_top": tuned,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_mixed(args, batch0, desc, launch):
+    """Mixed on-the-fly stream: every step renders a new batch of 1024 rooms
+    (fs 16/48 kHz, 2-8 mics, 1-3 sources, T60 0.1-1.0 s) through one
+    fixed-capacity hipGraph holding draw, render and backward.  Host planning
+    of the batches happens before the timed region; inside it each step
+    copies its descriptor and positions into the graph's buffers and replays."""
+    import numpy as np
+    import torch
+    from paper_2304_08052_amd import framrir as fr
+    from paper_2304_08052_amd import workloads as W
+    from paper_2304_08052_amd.stream import GraphStream
+    n_batches = min(args.steps, 8)
+    t0 = time.perf_counter()
+    plans = [fr.Plan(W.config5(k), launch=launch) for k in range(n_batches)]
+    plan_ms = (time.perf_counter() - t0) * 1e3 / n_batches
+    gs = GraphStream(n_rooms=1024, n_src_max=3, n_mic_max=8, rt60_max=1.0, fs_max=48000.0, launch=launch,
+                     backward=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3000)
+    gs.grad.normal_(generator=gen)          # synthetic upstream dL/dh
+    gs.load(plans[0])
+    gs.capture()
+    stream = torch.cuda.current_stream()
+    for k in range(args.warmup):
+        gs.load(plans[k % n_batches])
+        gs.replay()
+    torch.cuda.synchronize()
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_rirs = 0
+    t_start.record(stream)
+    for k in range(args.steps):
+        p = plans[k % n_batches]
+        gs.load(p)
+        gs.replay()
+        n_rirs += p.info.n_src
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end) / args.steps
+    value = n_rirs / (t_start.elapsed_time(t_end) * 1e-3)
+    line = {
+        "metric": "multi-channel RIRs/sec, mixed on-the-fly stream, forward + backward per hipGraph replay",
+        "value": value, "unit": "RIR/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "rooms_per_step": 1024, "distinct_batches": n_batches,
+                   "rirs_per_step": n_rirs / args.steps, "launch": gs.launch,
+                   "capacity_out_floats": int(gs.cap.info.out_floats)},
+        "plan_host_ms_per_batch": plan_ms,
     }
     print(json.dumps(line), flush=True)
 

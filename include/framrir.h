@@ -178,7 +178,7 @@ int framrir_draw(const framrir_plan* plan, const void* desc_dev, double* table_d
  * mic_dev [n_mic][3] and src_dev [n_src][3] FP64: positions to render with
  * (row 0 of each source is taken from src_dev, the other rows from the
  * table).  r_dev [n_rooms] FP64 or NULL (= the plan's r).  out_dev:
- * out_floats FP32, 16-byte aligned.  ws_dev: ws_bytes of device memory,
+ * out_floats FP32.  ws_dev: ws_bytes of device memory,
  * 256-byte aligned, initialised once by framrir_workspace_init (or zero
  * filled); every call leaves it initialised again.  Calls that share a
  * workspace must not overlap.  Samples are accumulated as fixed-point

@@ -1,0 +1,107 @@
+"""Launch-shape autotuner for the render kernel.
+
+A size class is the set of sample rates, the largest microphone count and the
+RIR-length range of a batch (those decide how items split into microphone
+groups and time tiles).  For a class, tune() times the render of a
+representative batch under each candidate launch shape (LDS tile budget,
+threads per workgroup, waves per SIMD, microphones per item) with HIP events
+and keeps the fastest.  Results are cached in a JSON file keyed by the GPU
+architecture and the size class: $FRAMRIR_TUNE_CACHE, else
+~/.cache/framrir/tune.json.
+"""
+import json
+import os
+
+import numpy as np
+
+from . import framrir as fr
+
+DEFAULT_CANDIDATES = [
+    dict(lds_bytes=lds, wg_threads=t, waves_per_simd=w, max_mic_group=g)
+    for (lds, t, w) in [(131072, 1024, 4), (98304, 1024, 4), (114688, 1024, 4), (65536, 1024, 8),
+                        (65536, 512, 4), (40960, 512, 8), (32768, 256, 4)]
+    for g in (8, 4)
+]
+
+
+def cache_path():
+    return os.environ.get("FRAMRIR_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "framrir", "tune.json"))
+
+
+def arch():
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def size_class(batch):
+    T = np.ceil(np.asarray(batch["rt60"]) * np.asarray(batch["fs"])).astype(np.int64)
+    fs = sorted({int(v) for v in np.asarray(batch["fs"])})
+    t_lo, t_hi = (int(2 ** np.floor(np.log2(T.min()))), int(2 ** np.ceil(np.log2(T.max()))))
+    return f"fs={'/'.join(map(str, fs))};mics<={int(np.max(batch['n_mic']))};T={t_lo}-{t_hi}"
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key, value):
+    data = _load()
+    data[key] = value
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_render(batch, launch, reps=5, warmup=2, params=None):
+    """Median render time (ms) of one batch under one launch shape."""
+    import torch
+    plan = fr.Plan(batch, params=params, launch=launch)
+    table, _, _ = plan.draw()
+    out, ws = plan.empty_out(), plan.workspace()
+    for _ in range(warmup):
+        plan.render(table, out=out, ws=ws)
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.render(table, out=out, ws=ws)
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
+def tune(batch, candidates=None, reps=5, params=None, store=True):
+    """Times every candidate on this batch; returns (best launch, results)."""
+    results = []
+    for cand in candidates or DEFAULT_CANDIDATES:
+        launch = dict(fr.DEFAULT_LAUNCH, **cand)
+        try:
+            ms = time_render(batch, launch, reps=reps, params=params)
+        except fr.FramrirError:      # shape not valid for this batch
+            continue
+        results.append((ms, launch))
+    results.sort(key=lambda r: r[0])
+    best = results[0][1]
+    if store:
+        _store(f"{arch()}|{size_class(batch)}", dict(launch=best, ms=results[0][0]))
+    return best, results
+
+
+def launch_for(batch, tune_if_missing=False, params=None):
+    """The cached best launch for this batch's size class (or the default)."""
+    hit = _load().get(f"{arch()}|{size_class(batch)}")
+    if hit is not None:
+        return dict(fr.DEFAULT_LAUNCH, **hit["launch"])
+    if tune_if_missing:
+        return tune(batch, params=params)[0]
+    return dict(fr.DEFAULT_LAUNCH)

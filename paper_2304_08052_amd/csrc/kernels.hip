@@ -814,7 +814,7 @@ int check_render_args(const framrir_plan* plan, const void* desc_dev, const doub
                       const double* src_dev, const void* out_dev, void* ws_dev, size_t ws_bytes, int64_t need) {
     if (!plan || !desc_dev || !table_dev || !mic_dev || !src_dev || !out_dev || !ws_dev)
         return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
-    if (!aligned(desc_dev, 256) || !aligned(table_dev, 32) || !aligned(ws_dev, 256) || !aligned(out_dev, 16))
+    if (!aligned(desc_dev, 256) || !aligned(table_dev, 32) || !aligned(ws_dev, 256) || !aligned(out_dev, 4))
         return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned buffer");
     if (static_cast<int64_t>(ws_bytes) < need)
         return fr_fail(FRAMRIR_E_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, static_cast<long long>(need));

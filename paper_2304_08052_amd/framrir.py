@@ -197,37 +197,42 @@ class Plan:
         return torch.zeros(n, dtype=torch.uint8, device=self.device)
 
     # ---- device calls ------------------------------------------------------
-    def draw(self, table=None, aux=False, words=False, stream=None):
+    # Every device call takes an optional desc: a device copy of another
+    # plan's descriptor blob launched with this plan's shapes (see stream.py).
+    def draw(self, table=None, aux=False, words=False, stream=None, desc=None):
         import torch
         table = self.empty_table() if table is None else table
         aux_t = torch.empty((self.info.n_img, 8), dtype=torch.float64, device=self.device) if aux else None
         w_t = torch.empty((self.info.n_img, 4), dtype=torch.int32, device=self.device) if words else None
-        _check(lib().framrir_draw(self._h, _ptr(self.desc), _ptr(table), _ptr(aux_t), _ptr(w_t),
-                                  _stream(stream)))
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_draw(self._h, _ptr(desc), _ptr(table), _ptr(aux_t), _ptr(w_t), _stream(stream)))
         return table, aux_t, w_t
 
-    def render(self, table, mic=None, src=None, r=None, out=None, ws=None, stream=None):
+    def render(self, table, mic=None, src=None, r=None, out=None, ws=None, stream=None, desc=None):
         out = self.empty_out() if out is None else out
         ws = self.workspace() if ws is None else ws
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
-        _check(lib().framrir_render(self._h, _ptr(self.desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_render(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
                                     _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out
 
-    def forward(self, table=None, mic=None, src=None, r=None, out=None, ws=None, stream=None):
+    def forward(self, table=None, mic=None, src=None, r=None, out=None, ws=None, stream=None, desc=None):
         table = self.empty_table() if table is None else table
         out = self.empty_out() if out is None else out
         ws = self.workspace() if ws is None else ws
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
-        _check(lib().framrir_forward(self._h, _ptr(self.desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_forward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
                                      _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out, table
 
-    def backward(self, table, grad_out, mic=None, src=None, r=None, ws=None, grads=None, stream=None):
+    def backward(self, table, grad_out, mic=None, src=None, r=None, ws=None, grads=None, stream=None, desc=None):
         import torch
         ws = self.workspace(backward=True) if ws is None else ws
+        desc = self.desc if desc is None else desc
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         if grads is None:
@@ -235,7 +240,7 @@ class Plan:
                      torch.empty((self.info.n_src, 3), dtype=torch.float32, device=self.device),
                      torch.empty(self.info.n_rooms, dtype=torch.float32, device=self.device))
         gm, gs, gr = grads
-        _check(lib().framrir_render_backward(self._h, _ptr(self.desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+        _check(lib().framrir_render_backward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
                                              _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws), ws.numel(),
                                              _stream(stream)))
         return gm, gs, gr
@@ -288,6 +293,40 @@ def host_philox4x32(ctr, key):
     out = np.empty_like(ctr)
     _check(lib().framrir_host_philox4x32(_np_ptr(ctr), _np_ptr(key), _np_ptr(out), ctr.shape[0]))
     return out
+
+
+def split_rooms(batch):
+    """One single-room batch per room (same arrays, sliced)."""
+    out = []
+    so = mo = 0
+    for b in range(len(batch["rt60"])):
+        ns, nm = int(batch["n_src"][b]), int(batch["n_mic"][b])
+        one = {k: batch[k][b:b + 1] for k in ("size", "rt60", "fs", "c", "r_override", "seed", "n_src", "n_mic")}
+        one["src"] = batch["src"][so:so + ns]
+        one["mic"] = batch["mic"][mo:mo + nm]
+        out.append(one)
+        so += ns
+        mo += nm
+    return out
+
+
+class PerRoom:
+    """The plain per-room launch path: one plan and one draw + render launch
+    sequence per room, the rooms one after another on one stream, writing
+    into slices of the same packed output as the batched path.  Same kernels;
+    no cross-room persistence and no graph."""
+
+    def __init__(self, batch, params=None, launch=None):
+        self.plans = [Plan(one, params, launch) for one in split_rooms(batch)]
+        self.tables = [p.empty_table() for p in self.plans]
+        self.ws = [p.workspace() for p in self.plans]
+        sizes = [p.info.out_floats for p in self.plans]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)])
+
+    def forward(self, out, stream=None):
+        for p, t, w, o0, o1 in zip(self.plans, self.tables, self.ws, self.offsets[:-1], self.offsets[1:]):
+            p.forward(table=t, out=out[int(o0):int(o1)], ws=w, stream=stream)
+        return out
 
 
 def simulate(batch, params=None, launch=None):
