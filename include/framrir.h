@@ -188,10 +188,26 @@ int framrir_render(const framrir_plan* plan, const void* desc_dev, const double*
                    const double* mic_dev, const double* src_dev, const double* r_dev,
                    float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Draw and render in one call (table_dev as for framrir_draw). */
+/* Draw and render in one call (table_dev as for framrir_draw): the draws
+ * run inside the preparation kernel (framrir_prepare with draw = 1), then
+ * framrir_render_prepared. */
 int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* table_dev,
                     const double* mic_dev, const double* src_dev, const double* r_dev,
                     float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The two halves of framrir_render.  framrir_prepare (one workgroup per
+ * source) computes, into the workspace, each source's fixed-point scale (a
+ * bound on the sum of its pulse amplitudes over the microphones) and an
+ * ordering of its table rows by delay; with draw != 0 it first draws the
+ * rows into table_dev (as framrir_draw).  framrir_render_prepared then
+ * renders; its workspace must hold the preparation of the same plan, table,
+ * positions and r.  Arguments and errors as for framrir_render. */
+int framrir_prepare(const framrir_plan* plan, const void* desc_dev, double* table_dev, const double* mic_dev,
+                    const double* src_dev, const double* r_dev, int draw, void* ws_dev, size_t ws_bytes,
+                    void* stream);
+int framrir_render_prepared(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                            const double* mic_dev, const double* src_dev, const double* r_dev, float* out_dev,
+                            void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Adjoint of framrir_render with the table held fixed.  grad_out_dev: dL/dh
  * in the output layout (FP32).  With u = (pos_i - mic_m) / D,

@@ -7,7 +7,8 @@ representative batch under each candidate launch shape (LDS tile budget,
 threads per workgroup, waves per SIMD, microphones per item) with HIP events
 and keeps the fastest.  Results are cached in a JSON file keyed by the GPU
 architecture and the size class: $FRAMRIR_TUNE_CACHE, else
-~/.cache/framrir/tune.json.
+~/.cache/framrir/tune.json.  launch_for() also consults tune_cache.json
+shipped beside this module (entries measured on MI355X).
 """
 import json
 import os
@@ -97,9 +98,19 @@ def tune(batch, candidates=None, reps=5, params=None, store=True):
     return best, results
 
 
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
 def launch_for(batch, tune_if_missing=False, params=None):
     """The cached best launch for this batch's size class (or the default)."""
-    hit = _load().get(f"{arch()}|{size_class(batch)}")
+    key = f"{arch()}|{size_class(batch)}"
+    hit = _load().get(key)
+    if hit is None:
+        try:
+            with open(SHIPPED) as f:
+                hit = json.load(f).get(key)
+        except (OSError, ValueError):
+            hit = None
     if hit is not None:
         return dict(fr.DEFAULT_LAUNCH, **hit["launch"])
     if tune_if_missing:

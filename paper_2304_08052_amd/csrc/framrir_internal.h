@@ -22,6 +22,7 @@ constexpr int kHalf = 40;          // taps are k - 40 .. k + 40 around k = floor
 constexpr int kHalo = 80;          // LDS guard samples on each side of a time tile
 constexpr int kListCap = 4096;     // largest number of image indices compacted per pass of a tile
 constexpr int kMaxMicGroup = 16;   // microphones per work item
+constexpr int kBuckets = 1024;     // delay buckets of the per-source row order
 constexpr int kPartialStride = 3 * kMaxMicGroup + 4;   // backward partials per item
 
 enum TauCode : int32_t { kTauQuarter = 0, kTauHalf = 1, kTauOne = 2 };

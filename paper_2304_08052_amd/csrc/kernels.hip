@@ -55,24 +55,13 @@ constexpr double kPiOver81 = 3.14159265358979323846 / 81.0;
 // ---------------------------------------------------------------------------
 // Draw stage
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) draw_kernel(const void* __restrict__ desc, double* __restrict__ table,
-                                                   double* __restrict__ aux, uint32_t* __restrict__ words,
-                                                   int* __restrict__ counters) {
-    const DescHeader* H = hdr(desc);
-    if (counters && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;
-    const int s = blockIdx.y;
-    if (s >= H->n_src) return;
-    const SrcDesc* S = srcs(desc) + s;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S->n_img) return;
-    const RoomDesc* R = rooms(desc) + S->room;
+// Table row i of source S (Sec. III-B, III-C; Eq. 3, 4, 6): row 0 is the
+// direct path, row i >= 1 the virtual source drawn from Philox counter
+// (i - 1, s, 0, 0).  Returns (x, y, z, g); fills aux / words when non-null.
+__device__ __forceinline__ double4 draw_row(const DescHeader* H, const SrcDesc* S, const RoomDesc* R, int i,
+                                            double* __restrict__ aux, uint32_t* __restrict__ words) {
     const int64_t row = S->img_off + i;
-    double* out = table + 4 * row;
     if (i == 0) {   // direct path: the source itself, no reflection (Sec. III-D)
-        out[0] = S->pos[0];
-        out[1] = S->pos[1];
-        out[2] = S->pos[2];
-        out[3] = 0.0;
         if (aux) {
             for (int k = 0; k < 8; ++k) aux[8 * row + k] = 0.0;
             aux[8 * row + 4] = 1.0;
@@ -80,7 +69,7 @@ __global__ void __launch_bounds__(256) draw_kernel(const void* __restrict__ desc
         }
         if (words)
             for (int k = 0; k < 4; ++k) words[4 * row + k] = 0u;
-        return;
+        return make_double4(S->pos[0], S->pos[1], S->pos[2], 0.0);
     }
     uint32_t x[4] = {static_cast<uint32_t>(i - 1), static_cast<uint32_t>(S->s_local), 0u, 0u};
     philox4x32_10(x, S->key0, S->key1);
@@ -110,10 +99,6 @@ __global__ void __launch_bounds__(256) draw_kernel(const void* __restrict__ desc
     double st, ctheta, sp, cp;
     sincospi_d(2.0 * u0, &st, &ctheta);
     sincospi_d(u1 - 0.5, &sp, &cp);
-    out[0] = R->centre[0] + dist * (cp * ctheta);
-    out[1] = R->centre[1] + dist * (cp * st);
-    out[2] = R->centre[2] + dist * sp;
-    out[3] = g;
     if (aux) {
         double* a = aux + 8 * row;
         a[0] = theta;
@@ -127,6 +112,20 @@ __global__ void __launch_bounds__(256) draw_kernel(const void* __restrict__ desc
     }
     if (words)
         for (int k = 0; k < 4; ++k) words[4 * row + k] = x[k];
+    return make_double4(R->centre[0] + dist * (cp * ctheta), R->centre[1] + dist * (cp * st),
+                        R->centre[2] + dist * sp, g);
+}
+
+__global__ void __launch_bounds__(256) draw_kernel(const void* __restrict__ desc, double* __restrict__ table,
+                                                   double* __restrict__ aux, uint32_t* __restrict__ words) {
+    const DescHeader* H = hdr(desc);
+    const int s = blockIdx.y;
+    if (s >= H->n_src) return;
+    const SrcDesc* S = srcs(desc) + s;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S->n_img) return;
+    const RoomDesc* R = rooms(desc) + S->room;
+    *reinterpret_cast<double4*>(table + 4 * (S->img_off + i)) = draw_row(H, S, R, i, aux, words);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,49 +423,168 @@ __device__ int compact_rows(const ItemCtx& c, int seg0, int seg1, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// Render
+// Render: fixed-point scale, preparation and the scatter kernel
 // ---------------------------------------------------------------------------
-// Fixed-point budget of the LDS accumulators of one work item: a bound on the
-// sum of |tap| over every pair bounds every sample, since the pulse never
-// exceeds 1 in magnitude; the bound plus the per-add rounding slack is mapped
-// just below 2^31.
+// Fixed-point budget of the LDS accumulators: a bound on the sum of |tap|
+// over every pair of a source bounds every sample of its RIRs, since the
+// pulse never exceeds 1 in magnitude; the bound plus the per-add rounding
+// slack is mapped just below 2^31.
 constexpr float kFixedBudget = 2147483648.0f - 262144.0f;
 constexpr float kBoundMargin = 1.0001f;
 
-// Upper bound of r^g / D over the microphones of a work item for one table
-// row: D >= |pos - centre| - rho (rho = largest |mic - centre| of the group);
-// rows inside that sphere fall back to the exact nearest microphone.
-__device__ __forceinline__ float row_amp_bound(const ItemCtx& c, double px, double py, double pz, float amp,
-                                               const double* __restrict__ micq) {
-    const float ex = static_cast<float>(px - c.cx), ey = static_cast<float>(py - c.cy),
-                ez = static_cast<float>(pz - c.cz);
-    float dmin = __builtin_sqrtf(__builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez))) * 0.999999f - c.rho;
-    if (dmin < 1e-3f) {
-        dmin = 3.0e38f;
-        for (int m = 0; m < c.w.n_mic; ++m) {
-            const float dx = static_cast<float>(px - micq[3 * m]), dy = static_cast<float>(py - micq[3 * m + 1]),
-                        dz = static_cast<float>(pz - micq[3 * m + 2]);
-            dmin = fminf(dmin, __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) * 0.999999f);
-        }
-    }
-    return amp / dmin;
+// ---------------------------------------------------------------------------
+// Render preparation: one workgroup per source.
+//   - the fixed-point scale of the source: budget / sum_i max_m r^g_i / D_im,
+//     with D_im >= |pos_i - centre| - rho (rho = largest |mic - centre| of
+//     the room), rows inside that sphere using the exact nearest microphone;
+//     summed in a fixed order, so the scale is reproducible;
+//   - a counting sort of the source's table rows by centre delay into
+//     kBuckets buckets: bucket offsets and a permutation.  A time tile then
+//     reads one contiguous range of rows, and the lanes of a wave add into
+//     nearby LDS addresses.  Order inside a bucket is arbitrary: the render
+//     accumulates integers, so its result does not depend on it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float prep_key_tc(const RoomDesc* R, double px, double py, double pz, float& dc) {
+    const float ex = static_cast<float>(px - R->centre[0]), ey = static_cast<float>(py - R->centre[1]),
+                ez = static_cast<float>(pz - R->centre[2]);
+    dc = __builtin_sqrtf(__builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
+    return dc * static_cast<float>(R->fs_over_c);
 }
 
+__device__ __forceinline__ int bucket_of(float tc, float inv_w) {
+    return min(kBuckets - 1, max(0, static_cast<int>(tc * inv_w)));
+}
+
+__device__ __forceinline__ float bucket_inv_width(int T) { return static_cast<float>(kBuckets) / (T + 256.0f); }
+
+constexpr int kKeyCap = 8192;   // rows whose bucket index stays in LDS between the passes
+
+// Row i of source s for the preparation: drawn here (and stored) when DRAW,
+// else read from the table; row 0 always takes the render-time source.
+template <bool DRAW>
+__device__ __forceinline__ double4 prep_row(const DescHeader* H, const SrcDesc* S, const RoomDesc* R, int s, int i,
+                                            double* __restrict__ table, const double* __restrict__ src,
+                                            bool store) {
+    double4 v;
+    if constexpr (DRAW) {
+        v = draw_row(H, S, R, i, nullptr, nullptr);
+        if (store) *reinterpret_cast<double4*>(table + 4 * (S->img_off + i)) = v;
+    } else {
+        if (i != 0) v = *reinterpret_cast<const double4*>(table + 4 * (S->img_off + i));
+    }
+    if (i == 0) v = make_double4(src[3 * s], src[3 * s + 1], src[3 * s + 2], 0.0);
+    return v;
+}
+
+template <bool DRAW>
+__global__ void __launch_bounds__(1024) prep_kernel(const void* __restrict__ desc, double* __restrict__ table,
+                                                    const double* __restrict__ mic, const double* __restrict__ src,
+                                                    const double* __restrict__ r_in, float* __restrict__ src_scale,
+                                                    int* __restrict__ bucket_off, int* __restrict__ perm) {
+    constexpr int NT = 1024;
+    static_assert(kBuckets == NT, "the bucket scan gives each thread one bucket");
+    __shared__ int cnt[kBuckets];
+    __shared__ unsigned short keys[kKeyCap];
+    __shared__ float red[NT / 64];
+    __shared__ int wsum[NT / 64];
+    __shared__ float s_rho;
+    const DescHeader* H = hdr(desc);
+    const int s = blockIdx.x;
+    if (s >= H->n_src) return;
+    const SrcDesc* S = srcs(desc) + s;
+    const RoomDesc* R = rooms(desc) + S->room;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    cnt[tid] = 0;
+    if (tid == 0) s_rho = 0.0f;
+    __syncthreads();
+    if (tid < R->n_mic) {   // rho = largest |mic - centre| of the room (positive floats order as ints)
+        const double* q = mic + 3 * (R->mic0 + tid);
+        const double ex = q[0] - R->centre[0], ey = q[1] - R->centre[1], ez = q[2] - R->centre[2];
+        atomicMax(reinterpret_cast<int*>(&s_rho), __float_as_int(static_cast<float>(__builtin_sqrt(ex * ex + ey * ey + ez * ez))));
+    }
+    const double r = r_in ? r_in[S->room] : R->r;
+    const double log2r = log2(r);
+    const float inv_w = bucket_inv_width(R->T);
+    const int n = S->n_img;
+    __syncthreads();
+    const float rhof = s_rho * 1.000001f + 1e-7f;
+    float bsum = 0.0f;
+    for (int i = tid; i < n; i += NT) {
+        const double4 v = prep_row<DRAW>(H, S, R, s, i, table, src, true);
+        float dc;
+        const float tc = prep_key_tc(R, v.x, v.y, v.z, dc);
+        const float amp = exp2f(static_cast<float>(v.w * log2r));
+        float dmin = dc * 0.999999f - rhof;
+        if (dmin < 1e-3f) {
+            dmin = 3.0e38f;
+            for (int m = 0; m < R->n_mic; ++m) {
+                const double* q = mic + 3 * (R->mic0 + m);
+                const float dx = static_cast<float>(v.x - q[0]), dy = static_cast<float>(v.y - q[1]),
+                            dz = static_cast<float>(v.z - q[2]);
+                dmin = fminf(dmin,
+                             __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) * 0.999999f);
+            }
+        }
+        bsum += amp / dmin;
+        const int key = bucket_of(tc, inv_w);
+        if (i < kKeyCap) keys[i] = static_cast<unsigned short>(key);
+        atomicAdd(&cnt[key], 1);
+    }
+    for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off);
+    if (lane == 0) red[wave] = bsum;
+    __syncthreads();
+    // exclusive scan of the bucket counts: one bucket per thread
+    const int c1 = cnt[tid];
+    int incl = c1;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int base = incl - c1;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    int* bo = bucket_off + static_cast<int64_t>(s) * (kBuckets + 1);
+    cnt[tid] = base;
+    bo[tid] = base;
+    if (tid == 0) {
+        bo[kBuckets] = n;
+        float b = 0.0f;
+        for (int w = 0; w < NT / 64; ++w) b += red[w];
+        b *= kBoundMargin;
+        src_scale[s] = (b > 0.0f && b < 3.0e38f) ? kFixedBudget / b : 0.0f;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {
+        int key;
+        if (i < kKeyCap) {
+            key = keys[i];
+        } else {   // recompute: the same arithmetic gives the same bucket
+            const double4 v = prep_row<DRAW>(H, S, R, s, i, table, src, false);
+            float dc;
+            key = bucket_of(prep_key_tc(R, v.x, v.y, v.z, dc), inv_w);
+        }
+        perm[S->img_off + atomicAdd(&cnt[key], 1)] = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Render
+// ---------------------------------------------------------------------------
 template <int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 render_kernel(const void* __restrict__ desc, const double* __restrict__ table, const double* __restrict__ mic,
               const double* __restrict__ src, const double* __restrict__ r_in, float* __restrict__ out,
-              int* __restrict__ counters, int acc_words, int list_cap) {
+              int* __restrict__ counters, const float* __restrict__ src_scale, const int* __restrict__ bucket_off,
+              const int* __restrict__ perm, int acc_words) {
     extern __shared__ int acc[];
-    int* list = acc + acc_words;
-    __shared__ int wave_cnt[NT / 64];
-    __shared__ float bound[NT / 64];
     __shared__ double micq[3 * kMaxMicGroup];
-    __shared__ float s_scale;
     __shared__ int s_item;
     const DescHeader* H = hdr(desc);
     const int n_items = H->n_items;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
+    // accumulators start at zero; each item's writeback clears what it used
+    for (int k = tid; k < acc_words; k += NT) acc[k] = 0;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&counters[0], 1);
         __syncthreads();
@@ -474,85 +592,76 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
         if (item >= n_items) break;
         ItemCtx c;
         load_item(desc, item, mic, r_in, c);
-        const int seg_cap = c.w.full ? c.n_img : list_cap;   // images compacted per pass of a tile
         const int mg = c.w.n_mic;
-        const int nacc = mg * c.rowlen;
-        for (int k = tid; k < nacc; k += NT) acc[k] = 0;
         if (tid < 3 * mg) micq[tid] = mic[3 * c.mic0_glob + tid];
         const int shift = kHalo - kHalf - c.w.t0;   // LDS index of tap 0 = k + shift
-        __syncthreads();
-        // ---- pass 1: bound of the sum of |taps| over the item (fixed order)
-        float bsum = 0.0f;
-        for (int seg0 = 0; seg0 < c.n_img; seg0 += seg_cap) {
-            const int seg1 = min(c.n_img, seg0 + seg_cap);
-            int n_list = seg1 - seg0;
-            if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
-            for (int e = tid; e < n_list; e += NT) {
-                const int i = c.w.full ? seg0 + e : list[e];
-                double px, py, pz, g;
-                image_row(c, i, table, src, c.w.src, px, py, pz, g);
-                const float amp = exp2f(static_cast<float>(g * c.log2r));
-                bsum += row_amp_bound(c, px, py, pz, amp, micq);
-            }
-            __syncthreads();
+        const float scale = src_scale[c.w.src];
+        // rows that can reach this tile: a contiguous range of the delay order
+        int lo = 0, hi = c.n_img;
+        if (!c.w.full) {
+            const float inv_w = bucket_inv_width(c.T);
+            const int b_lo = bucket_of(c.w.t0 - c.margin - 41.0f, inv_w);
+            const int b_hi = bucket_of((c.w.t0 + c.w.len + c.margin + 41.0f), inv_w);
+            const int* bo = bucket_off + static_cast<int64_t>(c.w.src) * (kBuckets + 1);
+            lo = bo[b_lo];
+            hi = bo[b_hi + 1];
         }
-        for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off);
-        if (lane == 0) bound[wave] = bsum;
+        const int* rows = perm + c.img_off + lo;
+        const int n_list = hi - lo;
+        // The range is in delay order; visiting it as j = e * P mod n_list
+        // (P prime, coprime to n_list) hands the lanes of a wave rows spread
+        // over the whole range, so their LDS adds rarely meet in one word.
+        int P = 97;                          // 97, 89, 83: their product exceeds any row count
+        while (n_list > 0 && n_list % P == 0) P = (P == 97) ? 89 : 83;
+        const int jstep = n_list > 0 ? static_cast<int>((static_cast<int64_t>(NT) * P) % n_list) : 0;
         __syncthreads();
-        if (tid == 0) {
-            float b = 0.0f;
-            for (int w = 0; w < NT / 64; ++w) b += bound[w];
-            b *= kBoundMargin;
-            s_scale = (b > 0.0f && b < 3.0e38f) ? kFixedBudget / b : 0.0f;
+        // ---- scatter the taps as rounded fixed-point integers.  Pair
+        // p = m * n_list + e: a wave takes rows of one microphone.
+        const int n_pairs = n_list * mg;
+        int p = tid, m = 0, e = tid;        // (m, e) of p = tid + k NT, advanced without division
+        while (e >= n_list && m < mg) {
+            e -= n_list;
+            ++m;
         }
-        __syncthreads();
-        const float scale = s_scale;
-        // ---- pass 2: scatter the taps as rounded fixed-point integers.  Pair
-        // p = m * n_list + e: a wave takes consecutive images of one microphone.
-        for (int seg0 = 0; seg0 < c.n_img; seg0 += seg_cap) {
-            const int seg1 = min(c.n_img, seg0 + seg_cap);
-            int n_list = seg1 - seg0;
-            if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
-            const int n_pairs = n_list * mg;
-            // (m, e) of pair p = tid + k NT, advanced without division
-            int p = tid, m = 0, e = tid;
+        int j = n_list > 0 ? static_cast<int>((static_cast<int64_t>(e) * P) % n_list) : 0;
+        double px = 0.0, py = 0.0, pz = 0.0, g = 0.0;
+        if (p < n_pairs) image_row(c, rows[j], table, src, c.w.src, px, py, pz, g);
+        while (p < n_pairs) {
+            const int cm = m;
+            const double cpx = px, cpy = py, cpz = pz, cg = g;
+            p += NT;
+            e += NT;
+            j += jstep;
+            if (j >= n_list) j -= n_list;
             while (e >= n_list && m < mg) {
                 e -= n_list;
                 ++m;
             }
-            double px = 0.0, py = 0.0, pz = 0.0, g = 0.0;
-            if (p < n_pairs) image_row(c, c.w.full ? seg0 + e : list[e], table, src, c.w.src, px, py, pz, g);
-            while (p < n_pairs) {
-                const int cm = m;
-                const double cpx = px, cpy = py, cpz = pz, cg = g;
-                p += NT;
-                e += NT;
-                while (e >= n_list && m < mg) {
-                    e -= n_list;
-                    ++m;
-                }
-                if (p < n_pairs)   // prefetch the next pair's row
-                    image_row(c, c.w.full ? seg0 + e : list[e], table, src, c.w.src, px, py, pz, g);
-                const float amp = exp2f(static_cast<float>(cg * c.log2r));
-                const Pair P = pair_setup(cpx, cpy, cpz, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2],
-                                          c.fs_over_c, amp);
-                const int b0 = P.k + shift;
-                if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
-                const float S = P.S * scale;
-                const float v0h = __builtin_fmaf((P.A * scale) * P.sinc, P.cy * P.cy, 0.5f);
-                fwd_taps(std::make_integer_sequence<int, kTaps>{}, acc + cm * c.rowlen + b0, P.dl, S, P.cy, P.sy,
-                         v0h);
-            }
-            __syncthreads();
+            if (p < n_pairs)   // prefetch the next pair's row
+                image_row(c, rows[j], table, src, c.w.src, px, py, pz, g);
+            const float amp = exp2f(static_cast<float>(cg * c.log2r));
+            const Pair P =
+                pair_setup(cpx, cpy, cpz, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2], c.fs_over_c, amp);
+            const int b0 = P.k + shift;
+            if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
+            const float S = P.S * scale;
+            const float v0h = __builtin_fmaf((P.A * scale) * P.sinc, P.cy * P.cy, 0.5f);
+            fwd_taps(std::make_integer_sequence<int, kTaps>{}, acc + cm * c.rowlen + b0, P.dl, S, P.cy, P.sy, v0h);
         }
-        // writeback of the tile core, samples [t0, min(t0 + len, T))
+        __syncthreads();
+        // writeback of the tile core, samples [t0, min(t0 + len, T)), and
+        // clearing of every accumulator the item touched
         const int nvalid = min(c.w.len, c.T - c.w.t0);
         const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
-        for (int m = 0; m < mg; ++m) {
-            float* dst = out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + m) * c.T +
+        for (int mm = 0; mm < mg; ++mm) {
+            float* dst = out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + mm) * c.T +
                          c.w.t0;
-            const int* srcrow = acc + m * c.rowlen + kHalo;
-            for (int n = tid; n < nvalid; n += NT) dst[n] = static_cast<float>(srcrow[n]) * inv;
+            int* row = acc + mm * c.rowlen;
+            for (int k = tid; k < c.rowlen; k += NT) {
+                const int v = row[k];
+                if (k >= kHalo && k < kHalo + nvalid) dst[k - kHalo] = static_cast<float>(v) * inv;
+                row[k] = 0;
+            }
         }
         __syncthreads();
     }
@@ -768,7 +877,7 @@ extern "C" int framrir_draw(const framrir_plan* plan, const void* desc_dev, doub
     const DescHeader& H = plan->header;
     const dim3 grid((H.max_img + 255) / 256, H.n_src);
     hipLaunchKernelGGL(draw_kernel, grid, dim3(256), 0, static_cast<hipStream_t>(stream), desc_dev, table_dev,
-                       aux_dev, words_dev, static_cast<int*>(nullptr));
+                       aux_dev, words_dev);
     return check_launch("draw_kernel");
 }
 
@@ -788,9 +897,37 @@ int allow_lds(F kernel) {
     return FRAMRIR_OK;
 }
 
+// Views of the render workspace (layout fixed by the plan's capacities).
+struct RenderWs {
+    int* counters;
+    float* src_scale;
+    int* bucket_off;
+    int* perm;
+};
+
+RenderWs render_ws(const framrir_plan* plan, void* ws_dev) {
+    char* b = static_cast<char*>(ws_dev);
+    return RenderWs{reinterpret_cast<int*>(b), reinterpret_cast<float*>(b + plan->ws_scale_off),
+                    reinterpret_cast<int*>(b + plan->ws_bucket_off), reinterpret_cast<int*>(b + plan->ws_perm_off)};
+}
+
+int launch_prepare(const framrir_plan* plan, const void* desc_dev, double* table_dev, const double* mic_dev,
+                   const double* src_dev, const double* r_dev, void* ws_dev, hipStream_t st, bool draw) {
+    const RenderWs w = render_ws(plan, ws_dev);
+    // preparation (and, for the forward, the draws themselves): one workgroup per source
+    if (draw)
+        hipLaunchKernelGGL(prep_kernel<true>, dim3(plan->header.n_src), dim3(1024), 0, st, desc_dev, table_dev,
+                           mic_dev, src_dev, r_dev, w.src_scale, w.bucket_off, w.perm);
+    else
+        hipLaunchKernelGGL(prep_kernel<false>, dim3(plan->header.n_src), dim3(1024), 0, st, desc_dev, table_dev,
+                           mic_dev, src_dev, r_dev, w.src_scale, w.bucket_off, w.perm);
+    return check_launch("prep_kernel");
+}
+
 int launch_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev, const double* mic_dev,
-                  const double* src_dev, const double* r_dev, float* out_dev, int* counters, hipStream_t st) {
-    const int lds = plan->launch.lds_bytes + 4 * plan->list_cap;
+                  const double* src_dev, const double* r_dev, float* out_dev, void* ws_dev, hipStream_t st) {
+    const RenderWs w = render_ws(plan, ws_dev);
+    const int lds = plan->launch.lds_bytes;
     const int acc_words = plan->launch.lds_bytes / 4;
     const dim3 grid(plan->grid), block(plan->launch.wg_threads);
     const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
@@ -799,7 +936,8 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
     case NT * 16 + WPE:                                                                                     \
         if (int rc = allow_lds(render_kernel<NT, WPE>)) return rc;                                          \
         hipLaunchKernelGGL((render_kernel<NT, WPE>), grid, block, lds, st, desc_dev, table_dev, mic_dev,   \
-                           src_dev, r_dev, out_dev, counters, acc_words, plan->list_cap);                   \
+                           src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off, w.perm,         \
+                           acc_words);                                                                      \
         break;
         FR_KERNEL_SHAPES(FR_CASE)
 #undef FR_CASE
@@ -823,31 +961,43 @@ int check_render_args(const framrir_plan* plan, const void* desc_dev, const doub
 
 }  // namespace
 
-extern "C" int framrir_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
-                              const double* mic_dev, const double* src_dev, const double* r_dev, float* out_dev,
-                              void* ws_dev, size_t ws_bytes, void* stream) {
+extern "C" int framrir_prepare(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                               const double* mic_dev, const double* src_dev, const double* r_dev, int draw,
+                               void* ws_dev, size_t ws_bytes, void* stream) {
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, table_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_bytes : 0);
+    if (rc) return rc;
+    return launch_prepare(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, ws_dev, static_cast<hipStream_t>(stream),
+                          draw != 0);
+}
+
+extern "C" int framrir_render_prepared(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                                       const double* mic_dev, const double* src_dev, const double* r_dev,
+                                       float* out_dev, void* ws_dev, size_t ws_bytes, void* stream) {
     int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
                                plan ? plan->ws_bytes : 0);
     if (rc) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int* counters = static_cast<int*>(ws_dev);
-    return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, counters, st);
+    return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws_dev,
+                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" int framrir_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                              const double* mic_dev, const double* src_dev, const double* r_dev, float* out_dev,
+                              void* ws_dev, size_t ws_bytes, void* stream) {
+    int rc = framrir_prepare(plan, desc_dev, const_cast<double*>(table_dev), mic_dev, src_dev, r_dev, 0, ws_dev,
+                             ws_bytes, stream);
+    if (rc) return rc;
+    return framrir_render_prepared(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws_dev, ws_bytes,
+                                   stream);
 }
 
 extern "C" int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* table_dev,
                                const double* mic_dev, const double* src_dev, const double* r_dev, float* out_dev,
                                void* ws_dev, size_t ws_bytes, void* stream) {
-    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
-                               plan ? plan->ws_bytes : 0);
+    int rc = framrir_prepare(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, 1, ws_dev, ws_bytes, stream);
     if (rc) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int* counters = static_cast<int*>(ws_dev);
-    const DescHeader& H = plan->header;
-    const dim3 grid((H.max_img + 255) / 256, H.n_src);
-    hipLaunchKernelGGL(draw_kernel, grid, dim3(256), 0, st, desc_dev, table_dev, static_cast<double*>(nullptr),
-                       static_cast<uint32_t*>(nullptr), counters);
-    if ((rc = check_launch("draw_kernel"))) return rc;
-    return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, counters, st);
+    return framrir_render_prepared(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws_dev, ws_bytes,
+                                   stream);
 }
 
 extern "C" int framrir_render_backward(const framrir_plan* plan, const void* desc_dev, const double* table_dev,

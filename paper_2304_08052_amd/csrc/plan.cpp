@@ -373,7 +373,10 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     plan->header = H;
 
     // ---- workspace
-    plan->ws_bytes = kWsCounterBytes;
+    plan->ws_scale_off = kWsCounterBytes;
+    plan->ws_bucket_off = align(plan->ws_scale_off + static_cast<int64_t>(sizeof(float)) * src_row);
+    plan->ws_perm_off = align(plan->ws_bucket_off + static_cast<int64_t>(sizeof(int32_t)) * src_row * (kBuckets + 1));
+    plan->ws_bytes = align(plan->ws_perm_off + static_cast<int64_t>(sizeof(int32_t)) * img_off);
     plan->ws_bwd_bytes = kWsCounterBytes + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
     // compaction list only for time-tiled items
     bool tiled = false;

@@ -33,6 +33,8 @@ struct framrir_plan {
     int64_t ws_bwd_bytes = 0;
     int32_t grid = 1;
     int32_t list_cap = 0;   // compacted image indices per tile pass (0: every item covers its whole RIR)
+    // render workspace layout: counters | per-source scale | bucket offsets | row permutation
+    int64_t ws_scale_off = 0, ws_bucket_off = 0, ws_perm_off = 0;
 };
 
 int fr_fail(int code, const char* fmt, ...);

@@ -60,6 +60,9 @@ EXPORTS = {
     "framrir_draw": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "framrir_render": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_forward": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_prepare": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                                               ctypes.c_void_p]),
+    "framrir_render_prepared": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_render_backward": (ctypes.c_int, [ctypes.c_void_p] * 11 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_workspace_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]),
@@ -228,6 +231,26 @@ class Plan:
         _check(lib().framrir_forward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
                                      _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out, table
+
+    def prepare(self, table, mic=None, src=None, r=None, ws=None, draw=False, stream=None, desc=None):
+        """framrir_prepare: per-source scales and row order (and the draws when draw=True)."""
+        ws = self.workspace() if ws is None else ws
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_prepare(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r), int(draw),
+                                     _ptr(ws), ws.numel(), _stream(stream)))
+        return ws
+
+    def render_prepared(self, table, mic=None, src=None, r=None, out=None, ws=None, stream=None, desc=None):
+        """framrir_render_prepared: the render kernel alone (after prepare)."""
+        out = self.empty_out() if out is None else out
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_render_prepared(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                             _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out
 
     def backward(self, table, grad_out, mic=None, src=None, r=None, ws=None, grads=None, stream=None, desc=None):
         import torch

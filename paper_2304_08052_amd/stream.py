@@ -77,8 +77,7 @@ class GraphStream:
     def step(self):
         """One eager step: draw, render (and backward) of the loaded batch."""
         cap = self.cap
-        cap.draw(self.table, desc=self.desc)
-        cap.render(self.table, mic=self.mic, src=self.src, out=self.out, ws=self.ws, desc=self.desc)
+        cap.forward(self.table, mic=self.mic, src=self.src, out=self.out, ws=self.ws, desc=self.desc)
         if self.backward:
             cap.backward(self.table, self.grad, mic=self.mic, src=self.src, ws=self.ws_b, grads=self.grads,
                          desc=self.desc)
