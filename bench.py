@@ -46,6 +46,7 @@ def parse_args():
     p.add_argument("--wg-threads", type=int, default=None)
     p.add_argument("--max-mic-group", type=int, default=None)
     p.add_argument("--waves-per-simd", type=int, default=None)
+    p.add_argument("--grid-wgs", type=int, default=None, help="workgroups of the persistent grid (0 = as many as fit)")
     p.add_argument("--tune", action="store_true", help="pick the launch shape with the autotuner first")
     p.add_argument("--per-room", action="store_true",
                    help="also time the plain per-room launch path on the same batch")
@@ -116,6 +117,8 @@ def main():
         launch["max_mic_group"] = args.max_mic_group
     if args.waves_per_simd:
         launch["waves_per_simd"] = args.waves_per_simd
+    if args.grid_wgs is not None:
+        launch["grid_wgs"] = args.grid_wgs
     if args.workload == "mixed":
         return run_mixed(args, batch, desc, launch)
     tuned = None
@@ -126,7 +129,7 @@ def main():
         from paper_2304_08052_amd import autotune
         best, results = autotune.tune(batch)
         launch = dict(best, **launch)
-        tuned = [dict(ms=round(ms, 4), **{k: v for k, v in l.items() if k != "grid_wgs"}) for ms, l in results[:5]]
+        tuned = [dict(ms=round(ms, 4), **l) for ms, l in results[:5]]
     t0 = time.perf_counter()
     plan = fr.Plan(batch, launch=launch)
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -138,14 +141,14 @@ def main():
 
     table = plan.empty_table()
     out = plan.empty_out()
-    ws = plan.workspace()
-    ws_b = plan.workspace(backward=True)
+    ws = plan.workspace(backward=not args.no_backward)   # the backward reuses the forward's preparation
     grad = torch.from_numpy(W.upstream_grad(info.out_floats)).cuda()
     stream = torch.cuda.current_stream()
-    if args.copy_probe_mb > 0:   # known traffic: N MiB read + N MiB written
+    if args.copy_probe_mb > 0:   # known traffic: N MiB read + N MiB written (one elementwise kernel)
         a = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.cuda.synchronize()
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -161,7 +164,7 @@ def main():
 
     def bwd_step():
         fwd_step()
-        plan.backward(table, grad, ws=ws_b)
+        plan.backward(table, grad, ws=ws, prepared=True)
 
     for _ in range(args.warmup):
         fwd_step()

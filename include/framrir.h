@@ -197,11 +197,13 @@ int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* tabl
 
 /* The two halves of framrir_render.  framrir_prepare (one workgroup per
  * source) computes, into the workspace, each source's fixed-point scale (a
- * bound on the sum of its pulse amplitudes over the microphones) and an
- * ordering of its table rows by delay; with draw != 0 it first draws the
- * rows into table_dev (as framrir_draw).  framrir_render_prepared then
- * renders; its workspace must hold the preparation of the same plan, table,
- * positions and r.  Arguments and errors as for framrir_render. */
+ * bound on the sum of its pulse amplitudes over the microphones) and a copy
+ * of its rows (row 0 at src_dev's position, amplitude r^g precomputed)
+ * ordered by delay; with draw != 0 it first draws the rows into table_dev
+ * (as framrir_draw).  framrir_render_prepared then renders from the
+ * workspace alone (table_dev and src_dev are not read); its workspace must
+ * hold the preparation of the same plan, table, positions and r.  Arguments
+ * and errors as for framrir_render. */
 int framrir_prepare(const framrir_plan* plan, const void* desc_dev, double* table_dev, const double* mic_dev,
                     const double* src_dev, const double* r_dev, int draw, void* ws_dev, size_t ws_bytes,
                     void* stream);
@@ -216,12 +218,25 @@ int framrir_render_prepared(const framrir_plan* plan, const void* desc_dev, cons
  *   dL/dsrc_s = -(the same sum over row 0 only)          -> grad_src_dev [n_src][3]
  *   dL/dr_b   = sum_{s,m,i} (g_i / r) A S0                -> grad_r_dev [n_rooms]
  * Outputs are FP32 and fully overwritten; any may be NULL.  Sums run in a
- * fixed order, so results are bitwise reproducible.  ws_dev: ws_bwd_bytes,
- * initialised as for framrir_render. */
+ * fixed order, so results are bitwise reproducible.  ws_dev: ws_bwd_bytes
+ * (its first ws_bytes laid out as the render workspace), initialised as for
+ * framrir_render.  Runs framrir_prepare (draw = 0) into ws_dev, then
+ * framrir_render_backward_prepared. */
 int framrir_render_backward(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
                             const double* mic_dev, const double* src_dev, const double* r_dev,
                             const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
                             float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The adjoint alone, reusing a preparation already in ws_dev (ws_bwd_bytes):
+ * the one a framrir_forward / framrir_render / framrir_prepare call on the
+ * same workspace left for the same plan, table, positions and r.  The
+ * positions and r of that preparation are the ones differentiated; mic_dev
+ * and r_dev must hold the same values.  Arguments, outputs and errors as for
+ * framrir_render_backward. */
+int framrir_render_backward_prepared(const framrir_plan* plan, const void* desc_dev, const double* mic_dev,
+                                     const double* r_dev, const float* grad_out_dev, float* grad_mic_dev,
+                                     float* grad_src_dev, float* grad_r_dev, void* ws_dev, size_t ws_bytes,
+                                     void* stream);
 
 /* Initialises the counters at the start of a render / backward workspace
  * (enqueues one small kernel; no host synchronisation). */

@@ -4,7 +4,8 @@ A size class is the set of sample rates, the largest microphone count and the
 RIR-length range of a batch (those decide how items split into microphone
 groups and time tiles).  For a class, tune() times the render of a
 representative batch under each candidate launch shape (LDS tile budget,
-threads per workgroup, waves per SIMD, microphones per item) with HIP events
+threads per workgroup, waves per SIMD, microphones per item, workgroups of
+the persistent grid) with HIP events
 and keeps the fastest.  Results are cached in a JSON file keyed by the GPU
 architecture and the size class: $FRAMRIR_TUNE_CACHE, else
 ~/.cache/framrir/tune.json.  launch_for() also consults tune_cache.json
@@ -17,11 +18,24 @@ import numpy as np
 
 from . import framrir as fr
 
+N_CU = 256            # MI355X compute units
+LDS_PER_CU = 163840   # bytes
+STATIC_LDS = 2048     # the kernels' static LDS, bound from above
+
+
+def _per_cu_max(lds, threads, waves_per_simd):
+    """Workgroups of one shape that fit a compute unit at once."""
+    return max(1, min(LDS_PER_CU // (lds + STATIC_LDS), waves_per_simd * 4 // (threads // 64)))
+
+
+# (LDS tile, threads, waves per SIMD) x microphones per item x resident
+# workgroups per CU (the persistent grid is that many per CU)
 DEFAULT_CANDIDATES = [
-    dict(lds_bytes=lds, wg_threads=t, waves_per_simd=w, max_mic_group=g)
+    dict(lds_bytes=lds, wg_threads=t, waves_per_simd=w, max_mic_group=g, grid_wgs=N_CU * k)
     for (lds, t, w) in [(131072, 1024, 4), (98304, 1024, 4), (114688, 1024, 4), (65536, 1024, 8),
-                        (65536, 512, 4), (40960, 512, 8), (32768, 256, 4)]
+                        (65536, 512, 4), (49152, 512, 8), (40960, 512, 8), (32768, 256, 4)]
     for g in (8, 4)
+    for k in range(1, _per_cu_max(lds, t, w) + 1)
 ]
 
 

@@ -20,7 +20,6 @@ namespace framrir {
 constexpr int kTaps = 81;
 constexpr int kHalf = 40;          // taps are k - 40 .. k + 40 around k = floor(t + 1/2)
 constexpr int kHalo = 80;          // LDS guard samples on each side of a time tile
-constexpr int kListCap = 4096;     // largest number of image indices compacted per pass of a tile
 constexpr int kMaxMicGroup = 16;   // microphones per work item
 constexpr int kBuckets = 1024;     // delay buckets of the per-source row order
 constexpr int kPartialStride = 3 * kMaxMicGroup + 4;   // backward partials per item

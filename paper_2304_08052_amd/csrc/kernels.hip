@@ -2,20 +2,23 @@
 //
 //   draw_kernel      Sec. III-B, III-C, Eq. 3, 4, 6: one thread per virtual
 //                    source; Philox4x32-10 words -> FP64 draws -> image table.
+//   prep_kernel      one workgroup per source: (optionally the draws,) the
+//                    fixed-point scale and the rows sorted by delay.
 //   render_kernel    Eq. 1, 8: persistent grid over work items (source,
 //                    microphone group, time tile); per (image, microphone) pair
 //                    an FP64 delay, then 81 windowed-sinc taps accumulated in an
 //                    LDS tile as fixed-point integers (ds_add_u32) under a
-//                    per-row scale that cannot overflow; coalesced writeback.
+//                    per-source scale that cannot overflow; coalesced writeback.
 //   backward_kernel  adjoint of the render with the image table held fixed:
-//                    per pair 81-tap dot products of dL/dh with P and P'.
-//   finalize_kernel  fixed-order reduction of the backward partials.
+//                    per pair 81-tap dot products of dL/dh with P and P', and
+//                    the fixed-order reduction of each room's partials.
 //
 // Compiled with -ffp-contract=off: FP64 draw arithmetic is rounded one
 // operation at a time, in the order the method states.  FMAs in the render
 // are written explicitly.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "../../include/framrir.h"
@@ -243,26 +246,38 @@ __device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, int* 
     (fwd_tap<J>(row, dl, S, cy, sy, v0), ...);
 }
 
-// ---- backward taps: s0 += G A P(x), s1 += G A P'(x), x = m - dl.  With
-// v(dl) = A P(m - dl) = S Q_m(dl) and dS/ddl = A cos(pi dl) = Ac,
-//   A P'(m - dl) = -dv/ddl = -(Ac Q_m + S Q_m').
-// Q_m' comes from the derivative of the same polynomial; the taps next to the
-// centre use the closed form
+// ---- backward taps: s0 = sum_m G_m A P(m - dl), s1 = sum_m G_m A P'(m - dl)
+// over the 81 taps of a pair (G_m: dL/dh at tap m).  With v = S Q_m(dl) and
+// dS/ddl = A cos(pi dl) = Ac, A P'(m - dl) = -dv/ddl = -(Ac Q_m + S Q_m').
+// For the polynomial taps the window folds into coefficient sums first,
+//   sum_m G_m Q_m(dl) = sum_k dl^k D_k,   D_k = sum_m G_m c_{m,k},
+// one FMA per coefficient, after which the sum and its derivative in dl are
+// one Horner pass over D:
+//   s0 += S p(dl),   s1 -= Ac p(dl) + S p'(dl),   p(dl) = sum_k D_k dl^k.
+// The taps next to the centre use the closed form
 //   A P'(x) = (1/x) [(-1)^m (A cos(pi dl) w + (2 pi/81) S sw cw) - A P(x)],
 //   w = cw^2, cw = cos(pi x/81), sw = sin(pi x/81).
+constexpr int poly_top() {
+    int d = 0;
+    for (int j = 0; j < kTaps; ++j) d = kPolyDeg[j] > d ? kPolyDeg[j] : d;
+    return d;
+}
+constexpr int kPolyTop = poly_top();
+
 template <int J, int K>
-__device__ __forceinline__ float tap_horner_deriv(float dl) {
-    constexpr float c = static_cast<float>((K + 1) * static_cast<double>(kPolyCoef[J][K + 1]));
-    if constexpr (K + 1 == kPolyDeg[J]) {
-        return c;
-    } else {
-        return __builtin_fmaf(tap_horner_deriv<J, K + 1>(dl), dl, c);
-    }
+__device__ __forceinline__ void fold_coef(float G, float (&D)[kPolyTop + 1]) {
+    if constexpr (K <= kPolyDeg[J]) D[K] = __builtin_fmaf(G, kPolyCoef[J][K], D[K]);
+}
+
+template <int J, int... K>
+__device__ __forceinline__ void fold_tap(float G, float (&D)[kPolyTop + 1], std::integer_sequence<int, K...>) {
+    (fold_coef<J, K>(G, D), ...);
 }
 
 template <int J>
-__device__ __forceinline__ void bwd_tap(const float* __restrict__ row, float cy, float sy, float dl, float S,
-                                        float Ac, float S2, float v0, float dp0, float& s0, float& s1) {
+__device__ __forceinline__ void bwd_tap(const float* __restrict__ row, float (&D)[kPolyTop + 1], float cy, float sy,
+                                        float dl, float S, float Ac, float S2, float v0, float dp0, float& s0,
+                                        float& s1) {
     constexpr int m = J - kHalf;
     const float G = row[J];
     if constexpr (m == 0) {
@@ -283,10 +298,7 @@ __device__ __forceinline__ void bwd_tap(const float* __restrict__ row, float cy,
         s0 = __builtin_fmaf(G, val, s0);
         s1 = __builtin_fmaf(G, dp, s1);
     } else {
-        const float q = tap_horner<J, 0>(dl);
-        const float dq = tap_horner_deriv<J, 0>(dl);
-        s0 = __builtin_fmaf(G, S * q, s0);
-        s1 = __builtin_fmaf(-G, __builtin_fmaf(Ac, q, S * dq), s1);
+        fold_tap<J>(G, D, std::make_integer_sequence<int, kPolyTop + 1>{});
     }
 }
 
@@ -294,7 +306,18 @@ template <int... J>
 __device__ __forceinline__ void bwd_taps(std::integer_sequence<int, J...>, const float* __restrict__ row, float cy,
                                          float sy, float dl, float S, float Ac, float S2, float v0, float dp0,
                                          float& s0, float& s1) {
-    (bwd_tap<J>(row, cy, sy, dl, S, Ac, S2, v0, dp0, s0, s1), ...);
+    float D[kPolyTop + 1];
+#pragma unroll
+    for (int k = 0; k <= kPolyTop; ++k) D[k] = 0.0f;
+    (bwd_tap<J>(row, D, cy, sy, dl, S, Ac, S2, v0, dp0, s0, s1), ...);
+    float p = D[kPolyTop], dp = 0.0f;
+#pragma unroll
+    for (int k = kPolyTop - 1; k >= 0; --k) {
+        dp = __builtin_fmaf(dp, dl, p);
+        p = __builtin_fmaf(p, dl, D[k]);
+    }
+    s0 = __builtin_fmaf(S, p, s0);
+    s1 = s1 - __builtin_fmaf(Ac, p, S * dp);
 }
 
 // cos(pi x) for |x| <= 1/2 from its Taylor series in z = (pi x)^2 (to z^8).
@@ -368,60 +391,6 @@ __device__ __forceinline__ void load_item(const void* desc, int item, const doub
     c.rho = static_cast<float>(mx) * 1.000001f + 1e-7f;
 }
 
-// Image position / reflection count of table row i (row 0 follows src).
-__device__ __forceinline__ void image_row(const ItemCtx& c, int i, const double* __restrict__ table,
-                                          const double* __restrict__ src, int src_glob, double& px, double& py,
-                                          double& pz, double& g) {
-    if (i == 0) {
-        px = src[3 * src_glob + 0];
-        py = src[3 * src_glob + 1];
-        pz = src[3 * src_glob + 2];
-        g = 0.0;
-    } else {
-        const double4 v = *reinterpret_cast<const double4*>(table + 4 * (c.img_off + i));
-        px = v.x;
-        py = v.y;
-        pz = v.z;
-        g = v.w;
-    }
-}
-
-// Deterministic compaction of the rows [seg0, seg1) whose pulses may reach
-// the tile core into list[]; returns the count.  Order: row index.
-template <int NT>
-__device__ int compact_rows(const ItemCtx& c, int seg0, int seg1, const double* __restrict__ table,
-                            const double* __restrict__ src, int* __restrict__ list, int* __restrict__ wave_cnt) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = NT / 64;
-    int total = 0;
-    const float lo = static_cast<float>(c.w.t0) - c.margin - 41.0f;
-    const float hi = static_cast<float>(c.w.t0 + c.w.len) + c.margin + 41.0f;
-    for (int base = seg0; base < seg1; base += NT) {
-        const int i = base + tid;
-        bool keep = false;
-        if (i < seg1) {
-            double px, py, pz, g;
-            image_row(c, i, table, src, c.w.src, px, py, pz, g);
-            const float ex = static_cast<float>(px - c.cx), ey = static_cast<float>(py - c.cy),
-                        ez = static_cast<float>(pz - c.cz);
-            const float tc = __builtin_sqrtf(ex * ex + ey * ey + ez * ez) * static_cast<float>(c.fs_over_c);
-            keep = tc >= lo && tc < hi;
-        }
-        const uint64_t mask = __ballot(keep);
-        const int before = __popcll(mask & ((uint64_t(1) << lane) - 1));
-        if (lane == 0) wave_cnt[wave] = __popcll(mask);
-        __syncthreads();
-        int off = total;
-        for (int k = 0; k < wave; ++k) off += wave_cnt[k];
-        int sum = 0;
-        for (int k = 0; k < NW; ++k) sum += wave_cnt[k];
-        if (keep) list[off + before] = i;
-        total += sum;
-        __syncthreads();
-    }
-    return total;
-}
-
 // ---------------------------------------------------------------------------
 // Render: fixed-point scale, preparation and the scatter kernel
 // ---------------------------------------------------------------------------
@@ -438,11 +407,12 @@ constexpr float kBoundMargin = 1.0001f;
 //     with D_im >= |pos_i - centre| - rho (rho = largest |mic - centre| of
 //     the room), rows inside that sphere using the exact nearest microphone;
 //     summed in a fixed order, so the scale is reproducible;
-//   - a counting sort of the source's table rows by centre delay into
-//     kBuckets buckets: bucket offsets and a permutation.  A time tile then
-//     reads one contiguous range of rows, and the lanes of a wave add into
-//     nearby LDS addresses.  Order inside a bucket is arbitrary: the render
-//     accumulates integers, so its result does not depend on it.
+//   - a counting sort of the source's rows by centre delay into kBuckets
+//     buckets: bucket offsets, and the rows themselves stored in that order
+//     as render rows (position, amplitude r^g as FP32).  A time tile then
+//     reads one contiguous, coalesced range of rows.  Order inside a bucket
+//     is arbitrary: the render accumulates integers, so its result does not
+//     depend on it.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float prep_key_tc(const RoomDesc* R, double px, double py, double pz, float& dc) {
     const float ex = static_cast<float>(px - R->centre[0]), ey = static_cast<float>(py - R->centre[1]),
@@ -458,6 +428,22 @@ __device__ __forceinline__ int bucket_of(float tc, float inv_w) {
 __device__ __forceinline__ float bucket_inv_width(int T) { return static_cast<float>(kBuckets) / (T + 256.0f); }
 
 constexpr int kKeyCap = 8192;   // rows whose bucket index stays in LDS between the passes
+
+// A render row in 32 bytes: image position (FP64), then the amplitude r^g
+// (FP32, low word) and the reflection count g (FP32, high word).
+__device__ __forceinline__ double4 pack_render_row(const double4& v, float amp) {
+    const unsigned long long lo = static_cast<unsigned>(__float_as_int(amp));
+    const unsigned long long hi = static_cast<unsigned>(__float_as_int(static_cast<float>(v.w)));
+    return make_double4(v.x, v.y, v.z, __longlong_as_double(static_cast<long long>(lo | (hi << 32))));
+}
+
+__device__ __forceinline__ float render_row_amp(double w) {
+    return __int_as_float(static_cast<int>(static_cast<unsigned long long>(__double_as_longlong(w))));
+}
+
+__device__ __forceinline__ float render_row_g(double w) {
+    return __int_as_float(static_cast<int>(static_cast<unsigned long long>(__double_as_longlong(w)) >> 32));
+}
 
 // Row i of source s for the preparation: drawn here (and stored) when DRAW,
 // else read from the table; row 0 always takes the render-time source.
@@ -476,17 +462,51 @@ __device__ __forceinline__ double4 prep_row(const DescHeader* H, const SrcDesc* 
     return v;
 }
 
+// Per-row accounting of the first pass: amplitude, the row's term of the
+// amplitude bound, and its delay bucket.
+__device__ __forceinline__ int prep_account(const RoomDesc* R, const double4& v, double log2r, float rhof,
+                                            float inv_w, const double* __restrict__ mic, float& amp, float& term) {
+    float dc;
+    const float tc = prep_key_tc(R, v.x, v.y, v.z, dc);
+    amp = exp2f(static_cast<float>(v.w * log2r));
+    float dmin = dc * 0.999999f - rhof;
+    if (dmin < 1e-3f) {
+        dmin = 3.0e38f;
+        for (int m = 0; m < R->n_mic; ++m) {
+            const double* q = mic + 3 * (R->mic0 + m);
+            const float dx = static_cast<float>(v.x - q[0]), dy = static_cast<float>(v.y - q[1]),
+                        dz = static_cast<float>(v.z - q[2]);
+            dmin = fminf(dmin, __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) * 0.999999f);
+        }
+    }
+    term = amp / dmin;
+    return bucket_of(tc, inv_w);
+}
+
+// The preparation runs kPrepThreads per source; each wave owns a contiguous
+// range of the source's rows.  Dynamic LDS: bucket indices (u16) of the
+// first key_cap rows.  kMaxImg: rows of a source at most (img_hi <= 65535,
+// plus the direct path).
+constexpr int kPrepThreads = 512;
+constexpr int kPrepWaves = kPrepThreads / 64;
+constexpr int kMaxImg = 65536;
+__host__ __device__ constexpr int prep_key_cap(int max_img) { return ((max_img < kKeyCap ? max_img : kKeyCap) + 1) & ~1; }
+__host__ __device__ constexpr int prep_dyn_lds(int max_img) { return 2 * prep_key_cap(max_img); }
+
 template <bool DRAW>
-__global__ void __launch_bounds__(1024) prep_kernel(const void* __restrict__ desc, double* __restrict__ table,
-                                                    const double* __restrict__ mic, const double* __restrict__ src,
-                                                    const double* __restrict__ r_in, float* __restrict__ src_scale,
-                                                    int* __restrict__ bucket_off, int* __restrict__ perm) {
-    constexpr int NT = 1024;
-    static_assert(kBuckets == NT, "the bucket scan gives each thread one bucket");
-    __shared__ int cnt[kBuckets];
-    __shared__ unsigned short keys[kKeyCap];
-    __shared__ float red[NT / 64];
-    __shared__ int wsum[NT / 64];
+__global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restrict__ desc, double* __restrict__ table,
+                                                            const double* __restrict__ mic,
+                                                            const double* __restrict__ src,
+                                                            const double* __restrict__ r_in,
+                                                            float* __restrict__ src_scale,
+                                                            int* __restrict__ bucket_off, int* __restrict__ row0_slot,
+                                                            int* __restrict__ room_done, double* __restrict__ sorted,
+                                                            int key_cap) {
+    constexpr int NT = kPrepThreads, NW = kPrepWaves, BPT = kBuckets / NT;
+    extern __shared__ unsigned short keys[];             // key_cap
+    __shared__ int hist[NW][kBuckets];                   // per-wave bucket counts, then per-wave cursors
+    __shared__ float red[NW];
+    __shared__ int wsum[NW];
     __shared__ float s_rho;
     const DescHeader* H = hdr(desc);
     const int s = blockIdx.x;
@@ -494,8 +514,11 @@ __global__ void __launch_bounds__(1024) prep_kernel(const void* __restrict__ des
     const SrcDesc* S = srcs(desc) + s;
     const RoomDesc* R = rooms(desc) + S->room;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    cnt[tid] = 0;
-    if (tid == 0) s_rho = 0.0f;
+    for (int k = tid; k < NW * kBuckets; k += NT) (&hist[0][0])[k] = 0;
+    if (tid == 0) {
+        s_rho = 0.0f;
+        if (S->s_local == 0) room_done[S->room] = 0;   // completion count of the room's backward items
+    }
     __syncthreads();
     if (tid < R->n_mic) {   // rho = largest |mic - centre| of the room (positive floats order as ints)
         const double* q = mic + 3 * (R->mic0 + tid);
@@ -506,65 +529,127 @@ __global__ void __launch_bounds__(1024) prep_kernel(const void* __restrict__ des
     const double log2r = log2(r);
     const float inv_w = bucket_inv_width(R->T);
     const int n = S->n_img;
+    const double4* trow = reinterpret_cast<const double4*>(table) + S->img_off;
+    const double4 src_row = make_double4(src[3 * s], src[3 * s + 1], src[3 * s + 2], 0.0);
+    // this wave's rows: [w0, w1), in runs of 64
+    const int per_wave = (((n + NW - 1) / NW) + 63) & ~63;
+    const int w0 = min(n, wave * per_wave), w1 = min(n, w0 + per_wave);
     __syncthreads();
     const float rhof = s_rho * 1.000001f + 1e-7f;
     float bsum = 0.0f;
-    for (int i = tid; i < n; i += NT) {
-        const double4 v = prep_row<DRAW>(H, S, R, s, i, table, src, true);
-        float dc;
-        const float tc = prep_key_tc(R, v.x, v.y, v.z, dc);
-        const float amp = exp2f(static_cast<float>(v.w * log2r));
-        float dmin = dc * 0.999999f - rhof;
-        if (dmin < 1e-3f) {
-            dmin = 3.0e38f;
-            for (int m = 0; m < R->n_mic; ++m) {
-                const double* q = mic + 3 * (R->mic0 + m);
-                const float dx = static_cast<float>(v.x - q[0]), dy = static_cast<float>(v.y - q[1]),
-                            dz = static_cast<float>(v.z - q[2]);
-                dmin = fminf(dmin,
-                             __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) * 0.999999f);
-            }
+    // pass 1: rows (drawn and stored when DRAW), bound terms, buckets and the
+    // wave's bucket counts
+    auto count_run = [&](int i, bool valid, const double4& v) {
+        if (valid) {
+            float amp, term;
+            const int key = prep_account(R, v, log2r, rhof, inv_w, mic, amp, term);
+            bsum += term;
+            if (i < key_cap) keys[i] = static_cast<unsigned short>(key);
+            atomicAdd(&hist[wave][key], 1);
         }
-        bsum += amp / dmin;
-        const int key = bucket_of(tc, inv_w);
-        if (i < kKeyCap) keys[i] = static_cast<unsigned short>(key);
-        atomicAdd(&cnt[key], 1);
+    };
+    if constexpr (DRAW) {
+#pragma unroll 1
+        for (int c = w0; c < w1; c += 64) {
+            const int i = c + lane;
+            const bool valid = i < w1;
+            double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (valid) v = prep_row<true>(H, S, R, s, i, table, src, true);
+            count_run(i, valid, v);
+        }
+    } else {
+        for (int c = w0; c < w1; c += 4 * 64) {   // four loads in flight per lane
+            double4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = c + 64 * k + lane;
+                v[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+                if (i < w1) v[k] = i == 0 ? src_row : trow[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (c + 64 * k < w1) count_run(c + 64 * k + lane, c + 64 * k + lane < w1, v[k]);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off);
     if (lane == 0) red[wave] = bsum;
     __syncthreads();
-    // exclusive scan of the bucket counts: one bucket per thread
-    const int c1 = cnt[tid];
-    int incl = c1;
+    // bucket totals, exclusive scan (BPT buckets per thread), then each
+    // wave's cursor: the bucket's start plus the earlier waves' counts
+    int tot[BPT], run = 0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        tot[j] = 0;
+        for (int w = 0; w < NW; ++w) tot[j] += hist[w][tid * BPT + j];
+        run += tot[j];
+    }
+    int incl = run;
     for (int off = 1; off < 64; off <<= 1) {
         const int v = __shfl_up(incl, off);
         if (lane >= off) incl += v;
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int base = incl - c1;
+    int base = incl - run;
     for (int w = 0; w < wave; ++w) base += wsum[w];
     int* bo = bucket_off + static_cast<int64_t>(s) * (kBuckets + 1);
-    cnt[tid] = base;
-    bo[tid] = base;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        const int b = tid * BPT + j;
+        bo[b] = base;
+        int cur = base;
+        for (int w = 0; w < NW; ++w) {
+            const int c = hist[w][b];
+            hist[w][b] = cur;
+            cur += c;
+        }
+        base += tot[j];
+    }
     if (tid == 0) {
         bo[kBuckets] = n;
         float b = 0.0f;
-        for (int w = 0; w < NT / 64; ++w) b += red[w];
+        for (int w = 0; w < NW; ++w) b += red[w];
         b *= kBoundMargin;
         src_scale[s] = (b > 0.0f && b < 3.0e38f) ? kFixedBudget / b : 0.0f;
     }
     __syncthreads();
-    for (int i = tid; i < n; i += NT) {
-        int key;
-        if (i < kKeyCap) {
-            key = keys[i];
-        } else {   // recompute: the same arithmetic gives the same bucket
-            const double4 v = prep_row<DRAW>(H, S, R, s, i, table, src, false);
-            float dc;
-            key = bucket_of(prep_key_tc(R, v.x, v.y, v.z, dc), inv_w);
+    // pass 2: each wave places its rows through its own cursors, runs of 64
+    // in row order.  Only this wave touches its cursors, and one LDS atomic
+    // instruction resolves its colliding lanes in a fixed order, so the
+    // layout, and every sum later taken over it, is a function of the input
+    // alone.  Rows come back from the table (for DRAW the lane's own stores
+    // of pass 1).
+    double4* dst = reinterpret_cast<double4*>(sorted) + S->img_off;
+    for (int c = w0; c < w1; c += 4 * 64) {
+        double4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = c + 64 * k + lane;
+            v[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (i < w1) v[k] = i == 0 ? src_row : trow[i];
         }
-        perm[S->img_off + atomicAdd(&cnt[key], 1)] = i;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (c + 64 * k >= w1) continue;   // uniform per wave
+            const int i = c + 64 * k + lane;
+            const bool valid = i < w1;
+            int key = 0;
+            float amp = 0.0f;
+            if (valid) {
+                if (i < key_cap) {
+                    key = keys[i];
+                    amp = exp2f(static_cast<float>(v[k].w * log2r));
+                } else {   // the same arithmetic on the same row gives the same bucket
+                    float term;
+                    key = prep_account(R, v[k], log2r, rhof, inv_w, mic, amp, term);
+                }
+            }
+            if (valid) {
+                const int slot = atomicAdd(&hist[wave][key], 1);
+                dst[slot] = pack_render_row(v[k], amp);
+                if (i == 0) row0_slot[s] = slot;   // where the direct path landed
+            }
+        }
     }
 }
 
@@ -576,7 +661,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 render_kernel(const void* __restrict__ desc, const double* __restrict__ table, const double* __restrict__ mic,
               const double* __restrict__ src, const double* __restrict__ r_in, float* __restrict__ out,
               int* __restrict__ counters, const float* __restrict__ src_scale, const int* __restrict__ bucket_off,
-              const int* __restrict__ perm, int acc_words) {
+              const double* __restrict__ sorted, int acc_words) {
     extern __shared__ int acc[];
     __shared__ double micq[3 * kMaxMicGroup];
     __shared__ int s_item;
@@ -606,7 +691,7 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
             lo = bo[b_lo];
             hi = bo[b_hi + 1];
         }
-        const int* rows = perm + c.img_off + lo;
+        const double4* rows = reinterpret_cast<const double4*>(sorted) + c.img_off + lo;
         const int n_list = hi - lo;
         // The range is in delay order; visiting it as j = e * P mod n_list
         // (P prime, coprime to n_list) hands the lanes of a wave rows spread
@@ -624,11 +709,11 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
             ++m;
         }
         int j = n_list > 0 ? static_cast<int>((static_cast<int64_t>(e) * P) % n_list) : 0;
-        double px = 0.0, py = 0.0, pz = 0.0, g = 0.0;
-        if (p < n_pairs) image_row(c, rows[j], table, src, c.w.src, px, py, pz, g);
+        double4 row = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (p < n_pairs) row = rows[j];
         while (p < n_pairs) {
             const int cm = m;
-            const double cpx = px, cpy = py, cpz = pz, cg = g;
+            const double4 cur = row;
             p += NT;
             e += NT;
             j += jstep;
@@ -637,11 +722,9 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
                 e -= n_list;
                 ++m;
             }
-            if (p < n_pairs)   // prefetch the next pair's row
-                image_row(c, rows[j], table, src, c.w.src, px, py, pz, g);
-            const float amp = exp2f(static_cast<float>(cg * c.log2r));
-            const Pair P =
-                pair_setup(cpx, cpy, cpz, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2], c.fs_over_c, amp);
+            if (p < n_pairs) row = rows[j];   // prefetch the next pair's row
+            const Pair P = pair_setup(cur.x, cur.y, cur.z, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2],
+                                      c.fs_over_c, render_row_amp(cur.w));
             const int b0 = P.k + shift;
             if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
             const float S = P.S * scale;
@@ -679,15 +762,77 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
+// Sums the partials of room b's items in the plan's fixed order (room_items)
+// into its gradient outputs.  scratch: at least 4 ints of LDS, staging the
+// item table in chunks so that the partial loads do not chain.
+template <int NT>
+__device__ void finalize_room(const void* __restrict__ desc, int b, const float* __restrict__ partials,
+                              float* __restrict__ grad_mic, float* __restrict__ grad_src, float* __restrict__ grad_r,
+                              int* __restrict__ scratch, int scratch_words) {
+    const RoomDesc* R = rooms(desc) + b;
+    const int32_t* ri = room_items(desc) + R->item0;
+    const WorkItem* it = items(desc);
+    const int n_mic3 = 3 * R->n_mic, n_src3 = 3 * R->n_src;
+    const int n_out = n_mic3 + n_src3 + 1;
+    const int chunk = scratch_words / 4;
+    for (int ob = 0; ob < n_out; ob += NT) {
+        const int o = ob + static_cast<int>(threadIdx.x);
+        float sum = 0.0f;
+        for (int j0 = 0; j0 < R->n_item; j0 += chunk) {
+            const int nj = min(chunk, R->n_item - j0);
+            __syncthreads();
+            for (int j = threadIdx.x; j < nj; j += NT) {
+                const int id = ri[j0 + j];
+                const WorkItem& w = it[id];
+                scratch[4 * j] = id;
+                scratch[4 * j + 1] = w.mic0;
+                scratch[4 * j + 2] = w.n_mic;
+                scratch[4 * j + 3] = w.src - R->src0;
+            }
+            __syncthreads();
+            if (o < n_out) {
+                for (int j = 0; j < nj; ++j) {
+                    const int id = scratch[4 * j], mic0 = scratch[4 * j + 1], nm = scratch[4 * j + 2],
+                              sl = scratch[4 * j + 3];
+                    int at;   // this item's partial feeding output o, or -1
+                    if (o < n_mic3) {
+                        const int m = o / 3 - mic0;
+                        at = (m >= 0 && m < nm) ? m * 3 + o % 3 : -1;
+                    } else if (o < n_mic3 + n_src3) {
+                        at = ((o - n_mic3) / 3 == sl) ? 3 * kMaxMicGroup + (o - n_mic3) % 3 : -1;
+                    } else {
+                        at = 3 * kMaxMicGroup + 3;
+                    }
+                    const float v = partials[static_cast<int64_t>(id) * kPartialStride + max(at, 0)];
+                    sum += at >= 0 ? v : 0.0f;
+                }
+            }
+        }
+        if (o < n_mic3) {
+            if (grad_mic) grad_mic[3 * R->mic0 + o] = sum;
+        } else if (o < n_mic3 + n_src3) {
+            if (grad_src) grad_src[3 * R->src0 + (o - n_mic3)] = sum;
+        } else if (o < n_out) {
+            if (grad_r) grad_r[b] = sum;
+        }
+    }
+}
+
+// Backward: per item, dL/dh of the tile core is staged in LDS and every
+// (row, microphone) pair of the item's delay range gathers s0 and s1 against
+// it; per-thread sums reduce in a fixed two-stage order into the item's
+// partials.  The last item of a room to finish (a per-room count) sums the
+// room's partials in the plan's order, so the gradients are bitwise
+// reproducible whatever the schedule.  Dynamic LDS: max(tile, 8 NT floats).
 template <int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
-backward_kernel(const void* __restrict__ desc, const double* __restrict__ table, const double* __restrict__ mic,
-                const double* __restrict__ src, const double* __restrict__ r_in, const float* __restrict__ gout,
-                float* __restrict__ partials, int* __restrict__ counters, int acc_words, int list_cap) {
+backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, const double* __restrict__ r_in,
+                const float* __restrict__ gout, const double* __restrict__ sorted, const int* __restrict__ bucket_off,
+                const int* __restrict__ row0_slot, int* __restrict__ room_done, float* __restrict__ partials,
+                int* __restrict__ counters, float* __restrict__ grad_mic, float* __restrict__ grad_src,
+                float* __restrict__ grad_r, int lds_words) {
     extern __shared__ float tile[];
-    int* list = reinterpret_cast<int*>(tile) + acc_words;
-    __shared__ int wave_cnt[NT / 64];
-    __shared__ int s_item;
+    __shared__ int s_item, s_last;
     const DescHeader* H = hdr(desc);
     const int n_items = H->n_items;
     const int tid = threadIdx.x;
@@ -698,7 +843,6 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ table,
         if (item >= n_items) break;
         ItemCtx c;
         load_item(desc, item, mic, r_in, c);
-        const int seg_cap = c.w.full ? c.n_img : list_cap;
         const int mg = c.w.n_mic;
         // dL/dh of the tile core; zero in the halo and beyond T, so that each
         // pair counts only the taps of this tile
@@ -711,6 +855,19 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ table,
                 tile[m * c.rowlen + k] = core ? g[n] : 0.0f;
             }
         }
+        // rows that can reach this tile: a contiguous range of the delay order
+        int lo = 0, hi = c.n_img;
+        if (!c.w.full) {
+            const float inv_w = bucket_inv_width(c.T);
+            const int b_lo = bucket_of(c.w.t0 - c.margin - 41.0f, inv_w);
+            const int b_hi = bucket_of((c.w.t0 + c.w.len + c.margin + 41.0f), inv_w);
+            const int* bo = bucket_off + static_cast<int64_t>(c.w.src) * (kBuckets + 1);
+            lo = bo[b_lo];
+            hi = bo[b_hi + 1];
+        }
+        const double4* rows = reinterpret_cast<const double4*>(sorted) + c.img_off + lo;
+        const int n_list = hi - lo;
+        const int row0 = row0_slot[c.w.src] - lo;   // the direct path, if in range
         const int ipp = NT / mg;
         const int my_m = tid % mg, my_slot = tid / mg;
         const double* mq = mic + 3 * (c.mic0_glob + my_m);
@@ -721,45 +878,45 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ table,
         const float inv_r = static_cast<float>(1.0 / c.r);
         float gmx = 0.f, gmy = 0.f, gmz = 0.f, gsx = 0.f, gsy = 0.f, gsz = 0.f, gr = 0.f;
         __syncthreads();
-        for (int seg0 = 0; seg0 < c.n_img; seg0 += seg_cap) {
-            const int seg1 = min(c.n_img, seg0 + seg_cap);
-            int n_list = seg1 - seg0;
-            if (!c.w.full) n_list = compact_rows<NT>(c, seg0, seg1, table, src, list, wave_cnt);
-            if (my_slot < ipp) {
-                for (int e = my_slot; e < n_list; e += ipp) {
-                    const int i = c.w.full ? seg0 + e : list[e];
-                    double px, py, pz, g;
-                    image_row(c, i, table, src, c.w.src, px, py, pz, g);
-                    const float amp = exp2f(static_cast<float>(g * c.log2r));
-                    const Pair P = pair_setup(px, py, pz, mx, my, mz, c.fs_over_c, amp);
-                    const int b0 = P.k + shift;
-                    if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
-                    const float cpd = cospi_small(P.dl);
-                    const float Ac = P.A * cpd;
-                    const float S2 = (2.0f * kPiF / 81.0f) * P.S;
-                    const float v0 = P.A * P.sinc * (P.cy * P.cy);
-                    // A P'(-dl): sinc'(-dl) w + sinc(dl) w'(-dl), w'(-dl) = (2 pi/81) sy cy
-                    const float dp0 = P.A * (-dsinc_small(P.dl) * (P.cy * P.cy) +
-                                             P.sinc * (2.0f * kPiF / 81.0f) * P.sy * P.cy);
-                    float s0 = 0.f, s1 = 0.f;
-                    bwd_taps(std::make_integer_sequence<int, kTaps>{}, row + b0, P.cy, P.sy, P.dl, P.S, Ac, S2, v0,
-                             dp0, s0, s1);
-                    const float q = __builtin_fmaf(fsc, s1, s0 / P.D);
-                    gmx = __builtin_fmaf(P.ux, q, gmx);
-                    gmy = __builtin_fmaf(P.uy, q, gmy);
-                    gmz = __builtin_fmaf(P.uz, q, gmz);
-                    if (i == 0) {
-                        gsx -= P.ux * q;
-                        gsy -= P.uy * q;
-                        gsz -= P.uz * q;
-                    }
-                    gr = __builtin_fmaf(static_cast<float>(g) * inv_r, s0, gr);
+        if (my_slot < ipp && my_slot < n_list) {
+            int e = my_slot;
+            double4 nxt = rows[e];
+            while (e < n_list) {
+                const double4 cur = nxt;
+                const int ce = e;
+                e += ipp;
+                if (e < n_list) nxt = rows[e];   // prefetch the next pair's row
+                const Pair P = pair_setup(cur.x, cur.y, cur.z, mx, my, mz, c.fs_over_c, render_row_amp(cur.w));
+                const int b0 = P.k + shift;
+                if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
+                const float cpd = cospi_small(P.dl);
+                const float Ac = P.A * cpd;
+                const float S2 = (2.0f * kPiF / 81.0f) * P.S;
+                const float v0 = P.A * P.sinc * (P.cy * P.cy);
+                // A P'(-dl): sinc'(-dl) w + sinc(dl) w'(-dl), w'(-dl) = (2 pi/81) sy cy
+                const float dp0 =
+                    P.A * (-dsinc_small(P.dl) * (P.cy * P.cy) + P.sinc * (2.0f * kPiF / 81.0f) * P.sy * P.cy);
+                float s0 = 0.f, s1 = 0.f;
+                bwd_taps(std::make_integer_sequence<int, kTaps>{}, row + b0, P.cy, P.sy, P.dl, P.S, Ac, S2, v0, dp0,
+                         s0, s1);
+                const float q = __builtin_fmaf(fsc, s1, s0 / P.D);
+                gmx = __builtin_fmaf(P.ux, q, gmx);
+                gmy = __builtin_fmaf(P.uy, q, gmy);
+                gmz = __builtin_fmaf(P.uz, q, gmz);
+                if (ce == row0) {
+                    gsx -= P.ux * q;
+                    gsy -= P.uy * q;
+                    gsz -= P.uz * q;
                 }
+                gr = __builtin_fmaf(render_row_g(cur.w) * inv_r, s0, gr);
             }
-            __syncthreads();
         }
-        // fixed-order reduction over the threads of each microphone
-        float* red = tile;   // reuse: NT x 7 floats
+        __syncthreads();
+        // two-stage fixed-order reduction.  Tasks: (microphone, axis) over
+        // the slots of that microphone, then source (3 axes) and r over all
+        // threads; each task in NC chunks, then the chunk sums in order.
+        float* red = tile;                 // NT x 7
+        float* red2 = tile + 7 * NT;       // n_task x NC
         red[tid * 7 + 0] = gmx;
         red[tid * 7 + 1] = gmy;
         red[tid * 7 + 2] = gmz;
@@ -767,18 +924,46 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ table,
         red[tid * 7 + 4] = gsy;
         red[tid * 7 + 5] = gsz;
         red[tid * 7 + 6] = gr;
+        const int n_task = 3 * mg + 4;
+        const int NC = max(1, min(NT / n_task, NT / 8));
+        __syncthreads();
+        if (tid < n_task * NC) {
+            const int task = tid / NC, ch = tid % NC;
+            float sum = 0.f;
+            if (task < 3 * mg) {            // microphone task: threads slot * mg + m
+                const int m = task / 3, k = task % 3;
+                const int s_lo = (ipp * ch) / NC, s_hi = (ipp * (ch + 1)) / NC;
+                for (int sl = s_lo; sl < s_hi; ++sl) sum += red[(sl * mg + m) * 7 + k];
+            } else {                        // source / r task: every thread
+                const int k = 3 + (task - 3 * mg), n = ipp * mg;
+                const int t_lo = (n * ch) / NC, t_hi = (n * (ch + 1)) / NC;
+                for (int t = t_lo; t < t_hi; ++t) sum += red[t * 7 + k];
+            }
+            red2[tid] = sum;
+        }
         __syncthreads();
         float* part = partials + static_cast<int64_t>(item) * kPartialStride;
-        if (tid < mg * 3) {
-            const int m = tid / 3, k = tid % 3;
+        if (tid < n_task) {
             float sum = 0.f;
-            for (int t = m; t < ipp * mg; t += mg) sum += red[t * 7 + k];
-            part[m * 3 + k] = sum;
-        } else if (tid >= 64 && tid < 68) {
-            const int k = tid - 64;   // 0..2 source, 3 r
-            float sum = 0.f;
-            for (int t = 0; t < ipp * mg; ++t) sum += red[t * 7 + 3 + k];
-            part[3 * kMaxMicGroup + k] = sum;
+            for (int ch = 0; ch < NC; ++ch) sum += red2[tid * NC + ch];
+            part[tid < 3 * mg ? tid : 3 * kMaxMicGroup + (tid - 3 * mg)] = sum;
+        }
+        // completion of the room: after the barrier one release fence
+        // publishes the item's partials and the item is counted; the last
+        // item of the room acquires and sums the room.  (Release and acquire
+        // fences, not full ones: an acquire at device scope invalidates the
+        // L2 of the XCD, so only the summing workgroup takes it.)
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            s_last = atomicAdd(&room_done[c.room], 1) == rooms(desc)[c.room].n_item - 1;
+        }
+        __syncthreads();
+        if (s_last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            finalize_room<NT>(desc, c.room, partials, grad_mic, grad_src, grad_r, reinterpret_cast<int*>(tile),
+                              lds_words);
+            if (tid == 0) atomicExch(&room_done[c.room], 0);
         }
         __syncthreads();
     }
@@ -788,45 +973,6 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ table,
         if (done == static_cast<int>(gridDim.x) - 1) {
             atomicExch(&counters[0], 0);
             atomicExch(&counters[1], 0);
-        }
-    }
-}
-
-// One workgroup per room: sums the partials of the room's items in the
-// plan's fixed order.
-__global__ void __launch_bounds__(256) finalize_kernel(const void* __restrict__ desc,
-                                                        const float* __restrict__ partials,
-                                                        float* __restrict__ grad_mic, float* __restrict__ grad_src,
-                                                        float* __restrict__ grad_r) {
-    const int b = blockIdx.x;
-    const DescHeader* H = hdr(desc);
-    if (b >= H->n_rooms) return;
-    const RoomDesc* R = rooms(desc) + b;
-    const int32_t* ri = room_items(desc) + R->item0;
-    const WorkItem* it = items(desc);
-    const int n_out = 3 * R->n_mic + 3 * R->n_src + 1;
-    for (int o = threadIdx.x; o < n_out; o += blockDim.x) {
-        float sum = 0.f;
-        if (o < 3 * R->n_mic) {
-            const int m = o / 3, k = o % 3;
-            for (int j = 0; j < R->n_item; ++j) {
-                const WorkItem& w = it[ri[j]];
-                if (m >= w.mic0 && m < w.mic0 + w.n_mic)
-                    sum += partials[static_cast<int64_t>(ri[j]) * kPartialStride + (m - w.mic0) * 3 + k];
-            }
-            if (grad_mic) grad_mic[3 * (R->mic0 + m) + k] = sum;
-        } else if (o < 3 * R->n_mic + 3 * R->n_src) {
-            const int s = (o - 3 * R->n_mic) / 3, k = (o - 3 * R->n_mic) % 3;
-            for (int j = 0; j < R->n_item; ++j) {
-                const WorkItem& w = it[ri[j]];
-                if (w.src == R->src0 + s)
-                    sum += partials[static_cast<int64_t>(ri[j]) * kPartialStride + 3 * kMaxMicGroup + k];
-            }
-            if (grad_src) grad_src[3 * (R->src0 + s) + k] = sum;
-        } else {
-            for (int j = 0; j < R->n_item; ++j)
-                sum += partials[static_cast<int64_t>(ri[j]) * kPartialStride + 3 * kMaxMicGroup + 3];
-            if (grad_r) grad_r[b] = sum;
         }
     }
 }
@@ -885,11 +1031,11 @@ namespace {
 
 // Raises a kernel's dynamic-LDS limit to the largest budget a plan may use,
 // once per kernel and process (the attribute is not a stream operation).
-template <typename F>
-int allow_lds(F kernel) {
-    static int status = [&] {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLdsBytes);
+template <auto Kernel, int Bytes = kMaxDynLdsBytes>
+int allow_lds() {
+    static int status = [] {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, Bytes);
         return e == hipSuccess ? 0 : static_cast<int>(e);
     }();
     if (status != 0)
@@ -902,25 +1048,38 @@ struct RenderWs {
     int* counters;
     float* src_scale;
     int* bucket_off;
-    int* perm;
+    int* row0_slot;
+    int* room_done;
+    double* sorted;
 };
 
 RenderWs render_ws(const framrir_plan* plan, void* ws_dev) {
     char* b = static_cast<char*>(ws_dev);
-    return RenderWs{reinterpret_cast<int*>(b), reinterpret_cast<float*>(b + plan->ws_scale_off),
-                    reinterpret_cast<int*>(b + plan->ws_bucket_off), reinterpret_cast<int*>(b + plan->ws_perm_off)};
+    return RenderWs{reinterpret_cast<int*>(b),
+                    reinterpret_cast<float*>(b + plan->ws_scale_off),
+                    reinterpret_cast<int*>(b + plan->ws_bucket_off),
+                    reinterpret_cast<int*>(b + plan->ws_row0_off),
+                    reinterpret_cast<int*>(b + plan->ws_room_off),
+                    reinterpret_cast<double*>(b + plan->ws_rows_off)};
 }
 
 int launch_prepare(const framrir_plan* plan, const void* desc_dev, double* table_dev, const double* mic_dev,
                    const double* src_dev, const double* r_dev, void* ws_dev, hipStream_t st, bool draw) {
     const RenderWs w = render_ws(plan, ws_dev);
     // preparation (and, for the forward, the draws themselves): one workgroup per source
-    if (draw)
-        hipLaunchKernelGGL(prep_kernel<true>, dim3(plan->header.n_src), dim3(1024), 0, st, desc_dev, table_dev,
-                           mic_dev, src_dev, r_dev, w.src_scale, w.bucket_off, w.perm);
-    else
-        hipLaunchKernelGGL(prep_kernel<false>, dim3(plan->header.n_src), dim3(1024), 0, st, desc_dev, table_dev,
-                           mic_dev, src_dev, r_dev, w.src_scale, w.bucket_off, w.perm);
+    const int key_cap = prep_key_cap(plan->header.max_img);
+    const int lds = prep_dyn_lds(plan->header.max_img);
+    if (draw) {
+        if (int rc = allow_lds<prep_kernel<true>, prep_dyn_lds(kMaxImg)>()) return rc;
+        hipLaunchKernelGGL(prep_kernel<true>, dim3(plan->header.n_src), dim3(kPrepThreads), lds, st, desc_dev, table_dev,
+                           mic_dev, src_dev, r_dev, w.src_scale, w.bucket_off, w.row0_slot, w.room_done, w.sorted,
+                           key_cap);
+    } else {
+        if (int rc = allow_lds<prep_kernel<false>, prep_dyn_lds(kMaxImg)>()) return rc;
+        hipLaunchKernelGGL(prep_kernel<false>, dim3(plan->header.n_src), dim3(kPrepThreads), lds, st, desc_dev, table_dev,
+                           mic_dev, src_dev, r_dev, w.src_scale, w.bucket_off, w.row0_slot, w.room_done, w.sorted,
+                           key_cap);
+    }
     return check_launch("prep_kernel");
 }
 
@@ -934,9 +1093,9 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
     switch (key) {
 #define FR_CASE(NT, WPE)                                                                                    \
     case NT * 16 + WPE:                                                                                     \
-        if (int rc = allow_lds(render_kernel<NT, WPE>)) return rc;                                          \
+        if (int rc = allow_lds<render_kernel<NT, WPE>>()) return rc;                                          \
         hipLaunchKernelGGL((render_kernel<NT, WPE>), grid, block, lds, st, desc_dev, table_dev, mic_dev,   \
-                           src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off, w.perm,         \
+                           src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off, w.sorted,         \
                            acc_words);                                                                      \
         break;
         FR_KERNEL_SHAPES(FR_CASE)
@@ -1000,6 +1159,39 @@ extern "C" int framrir_forward(const framrir_plan* plan, const void* desc_dev, d
                                    stream);
 }
 
+extern "C" int framrir_render_backward_prepared(const framrir_plan* plan, const void* desc_dev,
+                                                const double* mic_dev, const double* r_dev,
+                                                const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
+                                                float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (!plan || !desc_dev || !mic_dev || !grad_out_dev || !ws_dev)
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
+    if (!aligned(desc_dev, 256) || !aligned(ws_dev, 256) || !aligned(grad_out_dev, 4))
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned buffer");
+    if (static_cast<int64_t>(ws_bytes) < plan->ws_bwd_bytes)
+        return fr_fail(FRAMRIR_E_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes,
+                       static_cast<long long>(plan->ws_bwd_bytes));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const RenderWs w = render_ws(plan, ws_dev);
+    float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + plan->ws_part_off);
+    const int lds = std::max(plan->launch.lds_bytes, 32 * plan->launch.wg_threads);
+    const dim3 grid(plan->grid), block(plan->launch.wg_threads);
+    const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
+    switch (key) {
+#define FR_CASE(NT, WPE)                                                                                      \
+    case NT * 16 + WPE:                                                                                       \
+        if (int rc2 = allow_lds<backward_kernel<NT, WPE>>()) return rc2;                                        \
+        hipLaunchKernelGGL((backward_kernel<NT, WPE>), grid, block, lds, st, desc_dev, mic_dev, r_dev,       \
+                           grad_out_dev, w.sorted, w.bucket_off, w.row0_slot, w.room_done, partials,          \
+                           w.counters, grad_mic_dev, grad_src_dev, grad_r_dev, lds / 4);                      \
+        break;
+        FR_KERNEL_SHAPES(FR_CASE)
+#undef FR_CASE
+        default:
+            return fr_fail(FRAMRIR_E_UNSUPPORTED, "launch shape not compiled");
+    }
+    return check_launch("backward_kernel");
+}
+
 extern "C" int framrir_render_backward(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
                                        const double* mic_dev, const double* src_dev, const double* r_dev,
                                        const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
@@ -1007,29 +1199,11 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
     int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, grad_out_dev, ws_dev, ws_bytes,
                                plan ? plan->ws_bwd_bytes : 0);
     if (rc) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int* counters = static_cast<int*>(ws_dev);
-    float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + kWsCounterBytes);
-    const int lds = plan->launch.lds_bytes + 4 * plan->list_cap;
-    const int acc_words = plan->launch.lds_bytes / 4;
-    const dim3 grid(plan->grid), block(plan->launch.wg_threads);
-    const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
-    switch (key) {
-#define FR_CASE(NT, WPE)                                                                                     \
-    case NT * 16 + WPE:                                                                                      \
-        if (int rc2 = allow_lds(backward_kernel<NT, WPE>)) return rc2;                                       \
-        hipLaunchKernelGGL((backward_kernel<NT, WPE>), grid, block, lds, st, desc_dev, table_dev, mic_dev,  \
-                           src_dev, r_dev, grad_out_dev, partials, counters, acc_words, plan->list_cap);     \
-        break;
-        FR_KERNEL_SHAPES(FR_CASE)
-#undef FR_CASE
-        default:
-            return fr_fail(FRAMRIR_E_UNSUPPORTED, "launch shape not compiled");
-    }
-    if ((rc = check_launch("backward_kernel"))) return rc;
-    hipLaunchKernelGGL(finalize_kernel, dim3(plan->header.n_rooms), dim3(256), 0, st, desc_dev, partials,
-                       grad_mic_dev, grad_src_dev, grad_r_dev);
-    return check_launch("finalize_kernel");
+    rc = launch_prepare(plan, desc_dev, const_cast<double*>(table_dev), mic_dev, src_dev, r_dev, ws_dev,
+                        static_cast<hipStream_t>(stream), false);
+    if (rc) return rc;
+    return framrir_render_backward_prepared(plan, desc_dev, mic_dev, r_dev, grad_out_dev, grad_mic_dev,
+                                            grad_src_dev, grad_r_dev, ws_dev, ws_bytes, stream);
 }
 
 extern "C" int framrir_workspace_init(void* ws_dev, size_t ws_bytes, void* stream) {

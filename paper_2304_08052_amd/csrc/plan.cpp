@@ -127,9 +127,9 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     if (launch.wg_threads < 64 || launch.wg_threads > 1024 || launch.wg_threads % 64 != 0)
         return fr_fail(FRAMRIR_E_RANGE, "wg_threads must be a multiple of 64 in [64, 1024] (got %d)",
                        launch.wg_threads);
-    if (launch.lds_bytes < 4096 || launch.lds_bytes > kMaxDynLdsBytes - 4 * kListCap || launch.lds_bytes % 16 != 0)
+    if (launch.lds_bytes < 4096 || launch.lds_bytes > kMaxDynLdsBytes || launch.lds_bytes % 16 != 0)
         return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be a multiple of 16 in [4096, %d] (got %d)",
-                       kMaxDynLdsBytes - 4 * kListCap, launch.lds_bytes);
+                       kMaxDynLdsBytes, launch.lds_bytes);
     if (launch.waves_per_simd != 4 && launch.waves_per_simd != 8)
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "waves_per_simd must be 4 or 8 (got %d)", launch.waves_per_simd);
     if (launch.wg_threads != 256 && launch.wg_threads != 512 && launch.wg_threads != 1024)
@@ -375,16 +375,15 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     // ---- workspace
     plan->ws_scale_off = kWsCounterBytes;
     plan->ws_bucket_off = align(plan->ws_scale_off + static_cast<int64_t>(sizeof(float)) * src_row);
-    plan->ws_perm_off = align(plan->ws_bucket_off + static_cast<int64_t>(sizeof(int32_t)) * src_row * (kBuckets + 1));
-    plan->ws_bytes = align(plan->ws_perm_off + static_cast<int64_t>(sizeof(int32_t)) * img_off);
-    plan->ws_bwd_bytes = kWsCounterBytes + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
-    // compaction list only for time-tiled items
-    bool tiled = false;
-    for (const WorkItem& w : it) tiled = tiled || !w.full;
-    plan->list_cap = tiled ? std::min(kListCap, max_img) : 0;
+    plan->ws_row0_off = align(plan->ws_bucket_off + static_cast<int64_t>(sizeof(int32_t)) * src_row * (kBuckets + 1));
+    plan->ws_room_off = align(plan->ws_row0_off + static_cast<int64_t>(sizeof(int32_t)) * src_row);
+    plan->ws_rows_off = align(plan->ws_room_off + static_cast<int64_t>(sizeof(int32_t)) * n_rooms);
+    plan->ws_bytes = align(plan->ws_rows_off + static_cast<int64_t>(4 * sizeof(double)) * img_off);
+    plan->ws_part_off = plan->ws_bytes;
+    plan->ws_bwd_bytes = plan->ws_part_off + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
     int32_t grid = launch.grid_wgs;
     if (grid == 0) {
-        const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + 4 * plan->list_cap + kStaticLdsBytes);
+        const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + kStaticLdsBytes);
         const int per_cu_waves = launch.waves_per_simd * 4 / (launch.wg_threads / 64);
         const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
         grid = static_cast<int32_t>(std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu));

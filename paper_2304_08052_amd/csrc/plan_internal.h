@@ -32,9 +32,11 @@ struct framrir_plan {
     int64_t ws_bytes = 0;
     int64_t ws_bwd_bytes = 0;
     int32_t grid = 1;
-    int32_t list_cap = 0;   // compacted image indices per tile pass (0: every item covers its whole RIR)
-    // render workspace layout: counters | per-source scale | bucket offsets | row permutation
-    int64_t ws_scale_off = 0, ws_bucket_off = 0, ws_perm_off = 0;
+    // workspace layout: counters | per-source scale | bucket offsets | slot of
+    // row 0 | per-room completion counts | delay-ordered rows (ws_bytes: the
+    // render) | per-item partials (ws_bwd_bytes: the backward)
+    int64_t ws_scale_off = 0, ws_bucket_off = 0, ws_row0_off = 0, ws_room_off = 0, ws_rows_off = 0,
+            ws_part_off = 0;
 };
 
 int fr_fail(int code, const char* fmt, ...);

@@ -64,6 +64,7 @@ EXPORTS = {
                                                                ctypes.c_void_p]),
     "framrir_render_prepared": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_render_backward": (ctypes.c_int, [ctypes.c_void_p] * 11 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_render_backward_prepared": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_workspace_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_void_p]),
@@ -252,8 +253,14 @@ class Plan:
                                              _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out
 
-    def backward(self, table, grad_out, mic=None, src=None, r=None, ws=None, grads=None, stream=None, desc=None):
+    def backward(self, table, grad_out, mic=None, src=None, r=None, ws=None, grads=None, stream=None, desc=None,
+                 prepared=False):
+        """framrir_render_backward; with prepared=True framrir_render_backward_prepared,
+        reusing the preparation a forward / render / prepare call left in ws
+        (a backward-size workspace), and table / src are not read."""
         import torch
+        if prepared and ws is None:
+            raise ValueError("prepared=True needs the workspace the forward ran on")
         ws = self.workspace(backward=True) if ws is None else ws
         desc = self.desc if desc is None else desc
         mic = self.mic_dev if mic is None else mic
@@ -263,9 +270,14 @@ class Plan:
                      torch.empty((self.info.n_src, 3), dtype=torch.float32, device=self.device),
                      torch.empty(self.info.n_rooms, dtype=torch.float32, device=self.device))
         gm, gs, gr = grads
-        _check(lib().framrir_render_backward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                             _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws), ws.numel(),
-                                             _stream(stream)))
+        if prepared:
+            _check(lib().framrir_render_backward_prepared(self._h, _ptr(desc), _ptr(mic), _ptr(r), _ptr(grad_out),
+                                                          _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws), ws.numel(),
+                                                          _stream(stream)))
+        else:
+            _check(lib().framrir_render_backward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                                 _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws),
+                                                 ws.numel(), _stream(stream)))
         return gm, gs, gr
 
     # ---- views -------------------------------------------------------------

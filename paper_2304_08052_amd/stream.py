@@ -50,8 +50,7 @@ class GraphStream:
         self.mic = torch.zeros((info.n_mic, 3), dtype=torch.float64, device=dev)
         self.src = torch.zeros((info.n_src, 3), dtype=torch.float64, device=dev)
         self.out = torch.zeros(info.out_floats, dtype=torch.float32, device=dev)
-        self.ws = self.cap.workspace()
-        self.ws_b = self.cap.workspace(backward=True)
+        self.ws = self.cap.workspace(backward=backward)   # the backward reuses the forward's preparation
         self.grad = torch.zeros(info.out_floats, dtype=torch.float32, device=dev)
         self.grads = (torch.zeros((info.n_mic, 3), dtype=torch.float32, device=dev),
                       torch.zeros((info.n_src, 3), dtype=torch.float32, device=dev),
@@ -79,8 +78,8 @@ class GraphStream:
         cap = self.cap
         cap.forward(self.table, mic=self.mic, src=self.src, out=self.out, ws=self.ws, desc=self.desc)
         if self.backward:
-            cap.backward(self.table, self.grad, mic=self.mic, src=self.src, ws=self.ws_b, grads=self.grads,
-                         desc=self.desc)
+            cap.backward(self.table, self.grad, mic=self.mic, src=self.src, ws=self.ws, grads=self.grads,
+                         desc=self.desc, prepared=True)
 
     def capture(self):
         """Captures step() into a hipGraph (after one eager warm-up)."""

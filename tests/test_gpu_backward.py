@@ -100,3 +100,50 @@ def test_autograd_function():
     assert torch.allclose(mic.grad.float(), gm, rtol=1e-6, atol=0)
     assert torch.allclose(src.grad.float(), gs, rtol=1e-6, atol=0)
     assert torch.allclose(r.grad.float(), gr, rtol=1e-6, atol=0)
+
+
+def test_backward_prepared_reuses_forward_preparation():
+    """framrir_render_backward_prepared after a forward on the same workspace
+    equals the standalone backward bit for bit, on two calls in a row."""
+    torch, fr, batch, plan, table, rooms, oplans, G, _ = _setup(3)
+    say("backward_prepared vs standalone backward")
+    g = torch.from_numpy(G).cuda()
+    want = [t.clone() for t in plan.backward(table, g)]
+    ws = plan.workspace(backward=True)
+    out, table2 = plan.forward(ws=ws)
+    assert torch.equal(table2, table)
+    for call in range(2):
+        got = plan.backward(table2, g, ws=ws, prepared=True)
+        torch.cuda.synchronize()
+        for x, y in zip(got, want):
+            assert torch.equal(x, y), f"call {call}"
+
+
+def test_backward_config2_full_sampled():
+    """Full batched workload (256 rooms, 6 mics, 16 kHz) in the launch shape the
+    benchmark uses, forward + prepared backward; sampled rooms against the
+    FP64 oracle adjoint."""
+    import torch
+    from paper_2304_08052_amd import autotune
+    from paper_2304_08052_amd import framrir as fr
+    batch = W.config2()
+    launch = autotune.launch_for(batch)
+    say(f"config2 backward launch={launch}")
+    plan = fr.Plan(batch, launch=launch)
+    ws = plan.workspace(backward=True)
+    out, table = plan.forward(ws=ws)
+    G = W.upstream_grad(plan.info.out_floats)
+    gm, gs, gr = plan.backward(table, torch.from_numpy(G).cuda(), ws=ws, prepared=True)
+    torch.cuda.synchronize()
+    gm, gs, gr = gm.cpu().numpy(), gs.cpu().numpy(), gr.cpu().numpy()
+    prm = F.Params()
+    rooms = F.rooms_from_batch(batch)
+    for b in (0, 131, 255):
+        rm = rooms[b]
+        op = F.room_plan(rm, prm)
+        gh = G[plan.out_off[b]:plan.out_off[b + 1]].astype(np.float64).reshape(len(rm.src), len(rm.mic), op["T"])
+        wm, ws_, wr = F.adjoint_room(op, rm, gh)
+        mo, so = plan.mic_off, plan.src_off
+        em, es, er = rel(gm[mo[b]:mo[b + 1]], wm), rel(gs[so[b]:so[b + 1]], ws_), abs(gr[b] - wr) / abs(wr)
+        say(f"room {b}: mic {em:.2e} src {es:.2e} r {er:.2e}")
+        assert em <= GRAD_TOL and es <= GRAD_TOL and er <= GRAD_TOL

@@ -233,3 +233,23 @@ def test_forward_bitwise_reproducible():
     b = plan.render(table).clone()
     c = fr.Plan(batch, launch=dict(grid_wgs=13)).render(table)
     assert torch.equal(a, b) and torch.equal(a, c)
+
+
+@pytest.mark.parametrize("which", ["small_mixed", "config2"])
+def test_preparation_deterministic(which):
+    """The preparation (scales, bucket offsets, delay-ordered rows) is the same
+    bytes on every run, and the same whether it draws the rows itself or reads
+    them from a drawn table."""
+    import torch
+    from paper_2304_08052_amd import framrir as fr
+    batch = W.small_mixed(6, seed=21) if which == "small_mixed" else W.config2()
+    plan = fr.Plan(batch)
+    say(f"preparation determinism {which}")
+    table, _, _ = plan.draw()
+    runs = [plan.prepare(table, ws=plan.workspace(), draw=False).clone() for _ in range(3)]
+    t2 = plan.empty_table()
+    runs.append(plan.prepare(t2, ws=plan.workspace(), draw=True).clone())
+    torch.cuda.synchronize()
+    for k, w in enumerate(runs[1:]):
+        assert torch.equal(runs[0], w), f"run {k + 1}"
+    assert torch.equal(t2, table)
