@@ -32,13 +32,44 @@ FP32_PUBLISHED_PEAK_TFLOPS = 157.3
 FLOPS_PER_TAP = 11          # sub, rcp, 2 mul + FMA (window), FMA, mul, add
 
 
+KERNEL_SOURCES = ["kernels.hip", "framrir_internal.h", "tap_poly.h", "plan.cpp", "plan_internal.h"]
+HBM_PROFILE = os.path.join(HERE, "profiles", "render_kernel_batched256_hbm.md")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_2304_08052_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name, launch):
+    """HBM bytes per render launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy kernel of known size),
+    or None when the kernel sources, the workload or the launch shape differ
+    from the ones the counters were taken on."""
+    try:
+        with open(HBM_PROFILE) as f:
+            kv = dict(line.split(" = ", 1) for line in f.read().splitlines() if " = " in line)
+    except OSError:
+        return None
+    shape = " ".join(f"{k}={launch[k]}" for k in ("lds_bytes", "wg_threads", "grid_wgs", "max_mic_group",
+                                                  "waves_per_simd"))
+    if (kv.get("workload") != workload_name or kv.get("launch") != shape
+            or kv.get("source_sha256") != kernel_sources_sha256()):
+        return None
+    return int(kv["traffic_bytes"])
+
+
 def parse_args():
     p = argparse.ArgumentParser(description=__doc__)
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--workload", default="batched", choices=["batched", "long", "mixed", "one"])
-    p.add_argument("--cpu-rooms", type=int, default=64,
+    p.add_argument("--cpu-rooms", type=int, default=192,
                    help="rooms of the workload timed through the FP64 oracle on one host core (0 = skip)")
     p.add_argument("--no-graph", action="store_true")
     p.add_argument("--no-backward", action="store_true")
@@ -244,6 +275,11 @@ def main():
     value = n_rirs / (step_ms * 1e-3)
     achieved = taps * FLOPS_PER_TAP / (render_ms * 1e-3) / 1e12
     cpu = cpu_baseline(batch, args.cpu_rooms) if args.cpu_rooms > 0 else None
+    traffic = measured_traffic(args.workload, plan.launch)
+    # algorithmic render bytes: every image row (32 B) read once per microphone
+    # group of its source, every output sample (4 B) written once
+    groups = np.repeat(-(-batch["n_mic"] // plan.launch["max_mic_group"]), batch["n_src"]).astype(np.int64)
+    algo_bytes = int(np.sum(plan.n_img.astype(np.int64) * groups)) * 32 + out_bytes
 
     line = {
         "metric": METRIC,
@@ -277,7 +313,10 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_NONPACKED_PEAK_TFLOPS,
             "frac_of_published_157": achieved / FP32_PUBLISHED_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": os.path.relpath(HBM_PROFILE, HERE) if traffic else None,
+            "traffic_over_algorithmic": traffic / algo_bytes if traffic else None,
+            "algorithmic_bytes": algo_bytes,
             "tap_updates_per_launch": taps,
             "flops_per_tap": FLOPS_PER_TAP,
             "render_ms": render_ms,
