@@ -81,6 +81,8 @@ def parse_args():
     p.add_argument("--tune", action="store_true", help="pick the launch shape with the autotuner first")
     p.add_argument("--per-room", action="store_true",
                    help="also time the plain per-room launch path on the same batch")
+    p.add_argument("--early", action="store_true",
+                   help="also time the early-reverberation windows (Eq. 9) of the rendered batch")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="run one plain device copy of this many MiB first (reference for HBM counters)")
     return p.parse_args()
@@ -252,6 +254,17 @@ def main():
         torch.cuda.synchronize()
         fb_ms = t_start.elapsed_time(t_end) / args.steps
 
+    early_ms = None
+    if args.early:
+        early_buf, start_buf = plan.early(out)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for _ in range(args.steps):
+            plan.early(out, early=early_buf, start=start_buf)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        early_ms = t_start.elapsed_time(t_end) / args.steps
+
     per_room_ms = None
     if args.per_room:
         pr = fr.PerRoom(batch, launch=launch)
@@ -329,6 +342,7 @@ def main():
         "fwd_bwd_ms_per_step": fb_ms,
         "fwd_bwd_over_fwd": (fb_ms / eager_ms) if fb_ms else None,
         "per_room_ms_per_step": per_room_ms,
+        "early_ms": early_ms,
         "plan_host_ms": plan_ms,
         "autotune_top": tuned,
     }

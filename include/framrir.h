@@ -123,6 +123,9 @@ typedef struct framrir_plan_info {
     int64_t ws_bwd_bytes;  /* workspace for framrir_render_backward */
     int32_t max_T;         /* longest RIR */
     int32_t max_img;       /* largest I + 1 */
+    int64_t early_floats;  /* floats of the packed early-reverberation windows (framrir_early) */
+    int32_t n_chan;        /* sum over rooms of n_src * n_mic */
+    int32_t reserved;
 } framrir_plan_info;
 
 typedef struct framrir_plan framrir_plan; /* opaque, host memory */
@@ -149,6 +152,13 @@ int framrir_plan_get_info(const framrir_plan* plan, framrir_plan_info* info);
  * (I + 1 rows per source), img_off[n_src + 1], rrmax[n_src], d0[n_src]. */
 int framrir_plan_get_arrays(const framrir_plan* plan, int32_t* T, int64_t* out_off, double* r,
                             int32_t* n_img, int64_t* img_off, double* rrmax, double* d0);
+
+/* Layout of the early-reverberation windows (framrir_early; Eq. 9): room b's
+ * windows start at float early_off[b] (early_off[n_rooms] = early_floats) as
+ * [n_src][n_mic][width[b]], width = ceil(6 fs/1000) + ceil(50 fs/1000) + 1;
+ * its channels (source-major) are chan_off[b] .. chan_off[b + 1] - 1 of the
+ * start array.  Any pointer may be NULL. */
+int framrir_plan_get_early(const framrir_plan* plan, int64_t* early_off, int32_t* width, int32_t* chan_off);
 
 /* Host pointer to the descriptor blob (owned by the plan, desc_bytes long),
  * to be copied to 256-byte aligned device memory before the device calls. */
@@ -237,6 +247,19 @@ int framrir_render_backward_prepared(const framrir_plan* plan, const void* desc_
                                      const double* r_dev, const float* grad_out_dev, float* grad_mic_dev,
                                      float* grad_src_dev, float* grad_r_dev, void* ws_dev, size_t ws_bytes,
                                      void* stream);
+
+/* Early-reverberation filter of Eq. 9, at the output rate: for every
+ * (source s, mic m) channel, t0 = |src_s - mic_m| fs / c0 (FP64, correctly
+ * rounded square root, then one multiply and one divide) and the window
+ * n - ceil(t0) in [-ceil(6 fs/1000), ceil(50 fs/1000)] of the rendered RIR.
+ * out_dev: the RIRs of framrir_render / framrir_forward for the same plan and
+ * positions (FP32, packed layout).  early_dev: early_floats FP32 in the layout
+ * of framrir_plan_get_early; samples of the window outside [0, T) are 0, every
+ * float is written.  start_dev: n_chan int32, the output index of each
+ * channel's first window sample (may be negative), or NULL.  All device
+ * pointers; enqueue only.  Errors: INVALID_ARG. */
+int framrir_early(const framrir_plan* plan, const void* desc_dev, const double* mic_dev, const double* src_dev,
+                  const float* out_dev, float* early_dev, int32_t* start_dev, void* stream);
 
 /* Initialises the counters at the start of a render / backward workspace
  * (enqueues one small kernel; no host synchronisation). */

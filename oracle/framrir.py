@@ -420,3 +420,28 @@ def early_window(t_direct, fs):
     n - ceil(t0) in [-ceil(6 fs/1000), ceil(50 fs/1000)]."""
     k0 = math.ceil(t_direct)
     return k0 - math.ceil(6.0 * fs / 1000.0), k0 + math.ceil(50.0 * fs / 1000.0)
+
+
+def early_room(room, h):
+    """Early-reverberation filter of Eq. 9 for one room's RIRs h [S, M, T].
+
+    Reading R-23: the window is taken at the output rate (the paper states it
+    on its high-rate grid, r_h fs), and D_0 is the direct-path distance from
+    the source to each microphone, so t0 = D_0 fs / c0 per (source, mic).
+    h_e[n] = h[n] for lo <= n <= hi and 0 elsewhere; only the window can be
+    non-zero, so it is returned compactly: early [S, M, W] holds h_e[lo..hi]
+    (zero where n falls outside [0, T)) and start [S, M] holds lo."""
+    n_src, n_mic, t_len = h.shape
+    pre, post = math.ceil(6.0 * room.fs / 1000.0), math.ceil(50.0 * room.fs / 1000.0)
+    width = pre + post + 1
+    early = np.zeros((n_src, n_mic, width))
+    start = np.zeros((n_src, n_mic), dtype=np.int64)
+    for s in range(n_src):
+        for m in range(n_mic):
+            _, _, t, _ = pair_geometry(np.asarray(room.src[s], dtype=np.float64)[None, :], np.zeros(1),
+                                       room.mic[m], 0.5, room.fs, room.c)
+            lo, hi = early_window(float(t[0]), room.fs)
+            start[s, m] = lo
+            for n in range(max(lo, 0), min(hi, t_len - 1) + 1):
+                early[s, m, n - lo] = h[s, m, n]
+    return early, start

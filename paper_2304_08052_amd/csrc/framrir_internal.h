@@ -36,7 +36,10 @@ struct DescHeader {
     int32_t tau_code;
     int32_t max_img;           // largest I + 1 of the batch
     int32_t max_T;
-    int32_t pad0;
+    int32_t n_chan;            // sum over rooms of n_src * n_mic
+    int64_t early_floats;      // floats of the packed early-reverberation windows
+    int32_t max_early;         // longest early window (samples)
+    int32_t max_room_chan;     // largest n_src * n_mic of a room
 };
 
 struct RoomDesc {
@@ -47,7 +50,10 @@ struct RoomDesc {
     int32_t T, n_src, n_mic;
     int32_t src0, mic0;        // first global source / microphone row
     int32_t item0, n_item;     // range in room_items
-    int32_t pad0;
+    int32_t chan0;             // first (source, mic) channel of the room
+    double fs, c;              // sample rate and speed of sound (early window index)
+    int64_t early_off;         // first float of the room's early windows
+    int32_t early_pre, early_post;   // ceil(6 fs / 1000), ceil(50 fs / 1000) (Eq. 9)
 };
 
 struct SrcDesc {

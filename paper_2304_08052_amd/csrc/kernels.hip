@@ -977,6 +977,35 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
     }
 }
 
+// Early-reverberation windows (Eq. 9): blocks over (window chunk, room,
+// channel of the room), threads along the window.
+__global__ void __launch_bounds__(256) early_kernel(const void* __restrict__ desc, const double* __restrict__ mic,
+                                                    const double* __restrict__ src, const float* __restrict__ out,
+                                                    float* __restrict__ early, int32_t* __restrict__ start) {
+    const DescHeader* H = hdr(desc);
+    for (int b = blockIdx.y; b < H->n_rooms; b += gridDim.y) {
+        const RoomDesc* R = rooms(desc) + b;
+        const int n_chan = R->n_src * R->n_mic;
+        const int width = R->early_pre + R->early_post + 1;
+        for (int local = blockIdx.z; local < n_chan; local += gridDim.z) {
+            const int s = local / R->n_mic, m = local % R->n_mic;
+            // t0 = |src - mic| fs / c0, one rounding per operation in this order
+            const double* p = src + 3 * (R->src0 + s);
+            const double* q = mic + 3 * (R->mic0 + m);
+            const double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+            const double t0 = (sqrt_rn(dx * dx + dy * dy + dz * dz) * R->fs) / R->c;
+            const int64_t first = static_cast<int64_t>(__builtin_ceil(t0)) - R->early_pre;
+            const float* h = out + R->out_off + static_cast<int64_t>(local) * R->T;
+            float* e = early + R->early_off + static_cast<int64_t>(local) * width;
+            for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < width; j += gridDim.x * blockDim.x) {
+                const int64_t n = first + j;
+                e[j] = (n >= 0 && n < R->T) ? h[n] : 0.0f;
+            }
+            if (start && blockIdx.x == 0 && threadIdx.x == 0) start[R->chan0 + local] = static_cast<int32_t>(first);
+        }
+    }
+}
+
 __global__ void zero_counters_kernel(int* counters) {
     if (threadIdx.x < 2) counters[threadIdx.x] = 0;
 }
@@ -1204,6 +1233,22 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
     if (rc) return rc;
     return framrir_render_backward_prepared(plan, desc_dev, mic_dev, r_dev, grad_out_dev, grad_mic_dev,
                                             grad_src_dev, grad_r_dev, ws_dev, ws_bytes, stream);
+}
+
+extern "C" int framrir_early(const framrir_plan* plan, const void* desc_dev, const double* mic_dev,
+                             const double* src_dev, const float* out_dev, float* early_dev, int32_t* start_dev,
+                             void* stream) {
+    if (!plan || !desc_dev || !mic_dev || !src_dev || !out_dev || !early_dev)
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
+    if (!aligned(desc_dev, 256)) return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned descriptor");
+    const DescHeader& H = plan->header;
+    if (H.n_chan == 0) return FRAMRIR_OK;
+    const unsigned gx = static_cast<unsigned>(std::min(8, (H.max_early + 255) / 256));
+    const unsigned gy = static_cast<unsigned>(std::min(H.n_rooms, 65535));
+    const unsigned gz = static_cast<unsigned>(std::min(H.max_room_chan, 1024));
+    hipLaunchKernelGGL(early_kernel, dim3(gx, gy, gz), dim3(256), 0, static_cast<hipStream_t>(stream), desc_dev,
+                       mic_dev, src_dev, out_dev, early_dev, start_dev);
+    return check_launch("early_kernel");
 }
 
 extern "C" int framrir_workspace_init(void* ws_dev, size_t ws_bytes, void* stream) {

@@ -148,7 +148,8 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     std::vector<RoomDesc>& rd = plan->rooms;
     std::vector<SrcDesc>& sd = plan->srcs;
     rd.resize(n_rooms);
-    int64_t out_off = 0, img_off = 0;
+    int64_t out_off = 0, img_off = 0, early_off = 0;
+    int32_t chan_row = 0, max_early = 0, max_room_chan = 0;
     int32_t src_row = 0, mic_row = 0, max_img = 0, max_T = 0;
 
     for (int32_t b = 0; b < n_rooms; ++b) {
@@ -217,6 +218,12 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         R.n_mic = rm.n_mic;
         R.src0 = src_row;
         R.mic0 = mic_row;
+        R.chan0 = chan_row;
+        R.fs = rm.fs;
+        R.c = rm.c;
+        R.early_off = early_off;
+        R.early_pre = static_cast<int32_t>(std::ceil(6.0 * rm.fs / 1000.0));
+        R.early_post = static_cast<int32_t>(std::ceil(50.0 * rm.fs / 1000.0));
         const double ct = rm.c * rm.rt60;
         const double log10_r = std::log10(r);
         const double log10_ct = std::log10(ct);
@@ -277,6 +284,11 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
             sd.push_back(S);
         }
         out_off += static_cast<int64_t>(rm.n_src) * rm.n_mic * T;
+        const int32_t n_chan_room = rm.n_src * rm.n_mic;
+        early_off += static_cast<int64_t>(n_chan_room) * (R.early_pre + R.early_post + 1);
+        chan_row += n_chan_room;
+        max_early = std::max(max_early, R.early_pre + R.early_post + 1);
+        max_room_chan = std::max(max_room_chan, n_chan_room);
         src_row += rm.n_src;
         mic_row += rm.n_mic;
         max_T = std::max(max_T, T);
@@ -357,6 +369,10 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     H.tau_code = tau_code;
     H.max_img = max_img;
     H.max_T = max_T;
+    H.n_chan = chan_row;
+    H.early_floats = early_off;
+    H.max_early = max_early;
+    H.max_room_chan = max_room_chan;
     auto align = [](int64_t v) { return (v + 255) & ~int64_t(255); };
     H.room_bytes = align(sizeof(DescHeader));
     H.src_bytes = align(H.room_bytes + static_cast<int64_t>(sizeof(RoomDesc)) * n_rooms);
@@ -409,6 +425,23 @@ extern "C" int framrir_plan_get_info(const framrir_plan* plan, framrir_plan_info
     info->ws_bwd_bytes = plan->ws_bwd_bytes;
     info->max_T = H.max_T;
     info->max_img = H.max_img;
+    info->n_chan = H.n_chan;
+    info->early_floats = H.early_floats;
+    return FRAMRIR_OK;
+}
+
+extern "C" int framrir_plan_get_early(const framrir_plan* plan, int64_t* early_off, int32_t* width,
+                                      int32_t* chan_off) {
+    if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "plan is NULL");
+    const DescHeader& H = plan->header;
+    for (int32_t b = 0; b < H.n_rooms; ++b) {
+        const RoomDesc& R = plan->rooms[b];
+        if (early_off) early_off[b] = R.early_off;
+        if (width) width[b] = R.early_pre + R.early_post + 1;
+        if (chan_off) chan_off[b] = R.chan0;
+    }
+    if (early_off) early_off[H.n_rooms] = H.early_floats;
+    if (chan_off) chan_off[H.n_rooms] = H.n_chan;
     return FRAMRIR_OK;
 }
 

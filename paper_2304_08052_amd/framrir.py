@@ -43,7 +43,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_rooms", ctypes.c_int32), ("n_src", ctypes.c_int32), ("n_mic", ctypes.c_int32),
                 ("n_items", ctypes.c_int32), ("n_img", ctypes.c_int64), ("out_floats", ctypes.c_int64),
                 ("desc_bytes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64), ("ws_bwd_bytes", ctypes.c_int64),
-                ("max_T", ctypes.c_int32), ("max_img", ctypes.c_int32)]
+                ("max_T", ctypes.c_int32), ("max_img", ctypes.c_int32), ("early_floats", ctypes.c_int64),
+                ("n_chan", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 DEFAULT_PARAMS = dict(alpha=0.25, beta=1.0, a=-2.0, b=2.0, tau=0.25, img_lo=1024, img_hi=4096)
@@ -66,6 +67,8 @@ EXPORTS = {
     "framrir_render_backward": (ctypes.c_int, [ctypes.c_void_p] * 11 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_render_backward_prepared": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_workspace_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_plan_get_early": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "framrir_early": (ctypes.c_int, [ctypes.c_void_p] * 8),
     "framrir_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_host_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64]),
@@ -169,6 +172,11 @@ class Plan:
         _check(L.framrir_plan_get_arrays(self._h, _np_ptr(self.T), _np_ptr(self.out_off), _np_ptr(self.r),
                                          _np_ptr(self.n_img), _np_ptr(self.img_off), _np_ptr(self.rrmax),
                                          _np_ptr(self.d0)))
+        self.early_off = np.zeros(n + 1, dtype=np.int64)
+        self.early_width = np.zeros(n, dtype=np.int32)
+        self.chan_off = np.zeros(n + 1, dtype=np.int32)
+        _check(L.framrir_plan_get_early(self._h, _np_ptr(self.early_off), _np_ptr(self.early_width),
+                                        _np_ptr(self.chan_off)))
         self.n_src = np.asarray(batch["n_src"], dtype=np.int64)
         self.n_mic = np.asarray(batch["n_mic"], dtype=np.int64)
         self.src_off = np.concatenate([[0], np.cumsum(self.n_src)])
@@ -279,6 +287,25 @@ class Plan:
                                                  _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws),
                                                  ws.numel(), _stream(stream)))
         return gm, gs, gr
+
+    def early(self, out, early=None, start=None, mic=None, src=None, stream=None, desc=None):
+        """framrir_early: the Eq. 9 windows of rendered RIRs `out`; returns
+        (early [early_floats] FP32, start [n_chan] int32)."""
+        import torch
+        early = torch.empty(self.info.early_floats, dtype=torch.float32, device=self.device) if early is None \
+            else early
+        start = torch.empty(self.info.n_chan, dtype=torch.int32, device=self.device) if start is None else start
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_early(self._h, _ptr(desc), _ptr(mic), _ptr(src), _ptr(out), _ptr(early), _ptr(start),
+                                   _stream(stream)))
+        return early, start
+
+    def early_view(self, early, b):
+        """[S_b, M_b, W_b] view of room b's early windows."""
+        w = int(self.early_width[b])
+        return early[self.early_off[b]:self.early_off[b + 1]].view(int(self.n_src[b]), int(self.n_mic[b]), w)
 
     # ---- views -------------------------------------------------------------
     def room_view(self, out, b):

@@ -181,3 +181,22 @@ def test_host_cbrt_near_midpoints():
     got = fr.host_cbrt_rn(x)
     want = np.array([oracle_cbrt(float(v)) for v in x])
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("maker", [W.config1, lambda: W.small_mixed(8, seed=3), lambda: W.config5(0)])
+def test_early_layout_matches_oracle(maker):
+    # Eq. 9 windows: width ceil(6 fs/1000) + ceil(50 fs/1000) + 1 per room,
+    # packed [S][M][W] room after room, channels numbered room after room
+    batch = maker()
+    plan = fr.Plan(batch, device="cpu")
+    rooms = F.rooms_from_batch(batch)
+    off, chan = 0, 0
+    for b, rm in enumerate(rooms):
+        lo, hi = F.early_window(0.0, rm.fs)
+        width = hi - lo + 1
+        assert plan.early_width[b] == width
+        assert plan.early_off[b] == off and plan.chan_off[b] == chan
+        off += len(rm.src) * len(rm.mic) * width
+        chan += len(rm.src) * len(rm.mic)
+    assert plan.early_off[-1] == off == plan.info.early_floats
+    assert plan.chan_off[-1] == chan == plan.info.n_chan

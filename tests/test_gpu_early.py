@@ -1,0 +1,93 @@
+"""GPU parity of the early-reverberation windows (Eq. 9, reading R-23):
+window starts bit-exact with the oracle's FP64 decision, window values equal
+to the rendered RIR samples bit for bit (zero outside [0, T)), and against the
+oracle's early filter of its own RIRs within the RIR tolerance."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import framrir as F
+from paper_2304_08052_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RIR_TOL = 1e-5
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_starts(batch):
+    starts = []
+    for rm in F.rooms_from_batch(batch):
+        for s in range(len(rm.src)):
+            for m in range(len(rm.mic)):
+                _, _, t, _ = F.pair_geometry(rm.src[s][None, :], np.zeros(1), rm.mic[m], 0.5, rm.fs, rm.c)
+                starts.append(F.early_window(float(t[0]), rm.fs)[0])
+    return np.asarray(starts, dtype=np.int64)
+
+
+def _run(batch, launch=None):
+    import torch
+    from paper_2304_08052_amd import framrir as fr
+    plan = fr.Plan(batch, launch=launch)
+    out, table = plan.forward()
+    early, start = plan.early(out)
+    torch.cuda.synchronize()
+    return plan, out.cpu().numpy(), early.cpu().numpy(), start.cpu().numpy()
+
+
+def _check_windows_equal_output(plan, out, early, start):
+    ch = 0
+    for b in range(plan.n_rooms):
+        T, w = int(plan.T[b]), int(plan.early_width[b])
+        h = out[plan.out_off[b]:plan.out_off[b + 1]].reshape(-1, T)
+        e = early[plan.early_off[b]:plan.early_off[b + 1]].reshape(-1, w)
+        for k in range(h.shape[0]):
+            n = start[ch + k] + np.arange(w)
+            ok = (n >= 0) & (n < T)
+            want = np.zeros(w, dtype=np.float32)
+            want[ok] = h[k, n[ok]]
+            assert np.array_equal(e[k], want), f"room {b} channel {k}"
+        ch += h.shape[0]
+
+
+def _edge_batch():
+    # one room, T = 800: a mic 0.2 m from the source (window starts before 0)
+    # and one ~4.4 m away (window runs past T)
+    return dict(size=np.array([[6.0, 5.0, 3.0]]), rt60=np.array([0.05]), fs=np.array([16000.0]),
+                c=np.array([343.0]), r_override=np.array([np.nan]), seed=np.array([7], dtype=np.uint64),
+                n_src=np.array([1], dtype=np.int32), n_mic=np.array([2], dtype=np.int32),
+                src=np.array([[2.0, 2.0, 1.5]]), mic=np.array([[2.2, 2.0, 1.5], [5.5, 4.5, 2.5]]))
+
+
+@pytest.mark.parametrize("which", ["small_mixed", "edges"])
+def test_early_matches_oracle(which):
+    batch = W.small_mixed(6, seed=31) if which == "small_mixed" else _edge_batch()
+    say(f"early windows {which}")
+    plan, out, early, start = _run(batch)
+    assert np.array_equal(start.astype(np.int64), _oracle_starts(batch))
+    _check_windows_equal_output(plan, out, early, start)
+    prm = F.Params()
+    for b, rm in enumerate(F.rooms_from_batch(batch)):
+        h = F.render_room(F.room_plan(rm, prm), rm)
+        want, wstart = F.early_room(rm, h)
+        got = early[plan.early_off[b]:plan.early_off[b + 1]].reshape(want.shape)
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        say(f"room {b}: rel-L2 {err:.2e}")
+        assert err <= RIR_TOL
+    if which == "edges":
+        assert start[0] < 0 and start[1] + plan.early_width[0] > plan.T[0]
+
+
+@pytest.mark.parametrize("which", ["config2", "config3"])
+def test_early_full_workloads(which):
+    from paper_2304_08052_amd import autotune
+    batch = W.config2() if which == "config2" else W.config3()
+    say(f"early windows {which}")
+    plan, out, early, start = _run(batch, launch=autotune.launch_for(batch))
+    assert np.array_equal(start.astype(np.int64), _oracle_starts(batch))
+    _check_windows_equal_output(plan, out, early, start)
