@@ -361,6 +361,9 @@ def run_mixed(args, batch0, desc, launch):
     from paper_2304_08052_amd import workloads as W
     from paper_2304_08052_amd.stream import GraphStream
     n_batches = min(args.steps, 8)
+    if not launch:
+        from paper_2304_08052_amd import autotune
+        launch = autotune.launch_for_stream(1024, 3, 8, 1.0, 48000.0)
     t0 = time.perf_counter()
     plans = [fr.Plan(W.config5(k), launch=launch) for k in range(n_batches)]
     plan_ms = (time.perf_counter() - t0) * 1e3 / n_batches

@@ -115,9 +115,7 @@ def tune(batch, candidates=None, reps=5, params=None, store=True):
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
-def launch_for(batch, tune_if_missing=False, params=None):
-    """The cached best launch for this batch's size class (or the default)."""
-    key = f"{arch()}|{size_class(batch)}"
+def _lookup(key):
     hit = _load().get(key)
     if hit is None:
         try:
@@ -125,8 +123,26 @@ def launch_for(batch, tune_if_missing=False, params=None):
                 hit = json.load(f).get(key)
         except (OSError, ValueError):
             hit = None
+    return hit
+
+
+def launch_for(batch, tune_if_missing=False, params=None):
+    """The cached best launch for this batch's size class (or the default)."""
+    hit = _lookup(f"{arch()}|{size_class(batch)}")
     if hit is not None:
         return dict(fr.DEFAULT_LAUNCH, **hit["launch"])
     if tune_if_missing:
         return tune(batch, params=params)[0]
     return dict(fr.DEFAULT_LAUNCH)
+
+
+def stream_class(n_rooms, n_src_max, n_mic_max, rt60_max, fs_max):
+    """Size class of a fixed-capacity graph step (stream.GraphStream): its
+    launch shape serves every batch the capacity admits."""
+    return f"stream:rooms={n_rooms};src<={n_src_max};mics<={n_mic_max};rt60<={rt60_max:g};fs<={fs_max:g}"
+
+
+def launch_for_stream(n_rooms, n_src_max, n_mic_max, rt60_max, fs_max):
+    """The shipped or cached launch for a graph step of this capacity (or the default)."""
+    hit = _lookup(f"{arch()}|{stream_class(n_rooms, n_src_max, n_mic_max, rt60_max, fs_max)}")
+    return dict(fr.DEFAULT_LAUNCH, **hit["launch"]) if hit is not None else dict(fr.DEFAULT_LAUNCH)

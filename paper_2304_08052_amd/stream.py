@@ -31,14 +31,17 @@ class GraphStream:
     """Capacity buffers plus one captured step.
 
     n_rooms, n_src_max, n_mic_max, rt60_max, fs_max bound every batch that
-    load() accepts.  backward=True adds the adjoint of an L(h) whose dL/dh is
+    load() accepts; launch defaults to the tuned shape of that capacity.  backward=True adds the adjoint of an L(h) whose dL/dh is
     the `grad` buffer (filled by the caller)."""
 
     def __init__(self, n_rooms, n_src_max, n_mic_max, rt60_max, fs_max, params=None, launch=None,
                  backward=True):
         import torch
         self.params = dict(fr.DEFAULT_PARAMS, **(params or {}))
-        self.launch = dict(fr.DEFAULT_LAUNCH, **(launch or {}))
+        if launch is None:   # the tuned shape of this capacity class, if one is known
+            from .autotune import launch_for_stream
+            launch = launch_for_stream(n_rooms, n_src_max, n_mic_max, rt60_max, fs_max)
+        self.launch = dict(fr.DEFAULT_LAUNCH, **launch)
         cap_params = dict(self.params, img_lo=self.params["img_hi"])
         self.cap = fr.Plan(_capacity_batch(n_rooms, n_src_max, n_mic_max, rt60_max, fs_max),
                            params=cap_params, launch=self.launch)

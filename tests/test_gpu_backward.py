@@ -147,3 +147,43 @@ def test_backward_config2_full_sampled():
         em, es, er = rel(gm[mo[b]:mo[b + 1]], wm), rel(gs[so[b]:so[b + 1]], ws_), abs(gr[b] - wr) / abs(wr)
         say(f"room {b}: mic {em:.2e} src {es:.2e} r {er:.2e}")
         assert em <= GRAD_TOL and es <= GRAD_TOL and er <= GRAD_TOL
+
+
+def test_backward_config4_full_sampled():
+    """Differentiable workload at full size (128 rooms, 4 mics, loss against a
+    perturbed target) in the tuned launch shape: sampled rooms against the
+    FP64 oracle adjoint."""
+    import torch
+    from paper_2304_08052_amd import autotune
+    from paper_2304_08052_amd import framrir as fr
+    batch = W.config4()
+    pert = W.config4_target_perturbation(batch)
+    launch = autotune.launch_for(batch)
+    say(f"config4 backward launch={launch}")
+    plan = fr.Plan(batch, launch=launch)
+    ws = plan.workspace(backward=True)
+    out, table = plan.forward(ws=ws)
+    prm = F.Params()
+    rooms = F.rooms_from_batch(batch)
+    sample = (0, 64, 127)
+    h = out.cpu().numpy()
+    G = np.zeros(plan.info.out_floats, dtype=np.float32)
+    oracle = {}
+    for b, rm in enumerate(rooms):
+        op = F.room_plan(rm, prm) if b in sample else None
+        mo = plan.mic_off
+        if b in sample:
+            tgt = F.render_room(op, rm, mic=rm.mic + pert["mic_delta"][mo[b]:mo[b + 1]], r=op["r"] + pert["r_delta"])
+            G[plan.out_off[b]:plan.out_off[b + 1]] = (2.0 * (h[plan.out_off[b]:plan.out_off[b + 1]]
+                                                         - tgt.ravel())).astype(np.float32)
+            oracle[b] = (rm, op)
+    gm, gs, gr = plan.backward(table, torch.from_numpy(G).cuda(), ws=ws, prepared=True)
+    torch.cuda.synchronize()
+    gm, gs, gr = gm.cpu().numpy(), gs.cpu().numpy(), gr.cpu().numpy()
+    for b, (rm, op) in oracle.items():
+        gh = G[plan.out_off[b]:plan.out_off[b + 1]].astype(np.float64).reshape(len(rm.src), len(rm.mic), op["T"])
+        wm, ws_, wr = F.adjoint_room(op, rm, gh)
+        mo, so = plan.mic_off, plan.src_off
+        em, es, er = rel(gm[mo[b]:mo[b + 1]], wm), rel(gs[so[b]:so[b + 1]], ws_), abs(gr[b] - wr) / abs(wr)
+        say(f"room {b}: mic {em:.2e} src {es:.2e} r {er:.2e}")
+        assert em <= GRAD_TOL and es <= GRAD_TOL and er <= GRAD_TOL
