@@ -84,7 +84,9 @@ typedef struct framrir_room {
  * alpha, beta of Eq. 3 (0 <= alpha < beta <= 1), a <= b of the perturbation
  * p ~ U(a, b) in Eq. 6, tau of Eq. 6 (0.25, 0.5 or 1), and the range of the
  * per-source image count I ~ U_int[img_lo, img_hi] (0 <= img_lo <= img_hi
- * <= 65535).  taps must be 81.  flags must be 0. */
+ * <= 65535).  taps must be 81.  flags: 0, or FRAMRIR_FLAG_MULTIRATE for a
+ * plan of the paper-literal multi-rate rendering (framrir_forward_multirate). */
+#define FRAMRIR_FLAG_MULTIRATE 1u
 typedef struct framrir_params {
     double alpha, beta, a, b, tau;
     int32_t img_lo, img_hi;
@@ -125,7 +127,9 @@ typedef struct framrir_plan_info {
     int32_t max_img;       /* largest I + 1 */
     int64_t early_floats;  /* floats of the packed early-reverberation windows (framrir_early) */
     int32_t n_chan;        /* sum over rooms of n_src * n_mic */
-    int32_t reserved;
+    int32_t multirate;     /* 1 for a FRAMRIR_FLAG_MULTIRATE plan */
+    int64_t mr_floats;     /* multi-rate plans: floats of one intermediate signal at r_l fs */
+    int64_t ws_mr_bytes;   /* multi-rate plans: workspace of framrir_forward_multirate */
 } framrir_plan_info;
 
 typedef struct framrir_plan framrir_plan; /* opaque, host memory */
@@ -260,6 +264,31 @@ int framrir_render_backward_prepared(const framrir_plan* plan, const void* desc_
  * pointers; enqueue only.  Errors: INVALID_ARG. */
 int framrir_early(const framrir_plan* plan, const void* desc_dev, const double* mic_dev, const double* src_dev,
                   const float* out_dev, float* early_dev, int32_t* start_dev, void* stream);
+
+/* The paper-literal multi-rate rendering (Sec. II, Sec. III-D, Eq. 7-8) for a
+ * plan made with FRAMRIR_FLAG_MULTIRATE: per room r_h = floor(10^6 / fs),
+ * r_l = floor(sqrt(r_h)) (at most 12), L = ceil(T60 r_h fs).  Draws as
+ * framrir_forward; then per (image, mic) pair q = min(ceil(D / c0 r_h fs),
+ * L - 1) (D correctly rounded, FP64), the impulse r^g / D at q down-sampled to
+ * r_l fs with the 81-tap Hann-windowed sinc (unit peak) into inter_dev[0 ..
+ * mr_floats) (packed [S][M][T_l], T_l = ceil(T60 r_l fs)), an 80 Hz
+ * second-order Butterworth high-pass (bilinear, prewarped; FP64 recurrence,
+ * exact chunked evaluation, its zero-state chunks in inter_dev[mr_floats ..
+ * 2 mr_floats) as scratch), and the decimation by r_l with the same pulse in
+ * units of fs: out_dev (out_floats FP32, packed [S][M][T], T = ceil(T60 fs)).
+ * inter_dev: 2 * mr_floats FP32; ws_dev: ws_mr_bytes, initialised as for
+ * framrir_render.  Enqueue only.  Errors: INVALID_ARG, WORKSPACE,
+ * UNSUPPORTED (not a multi-rate plan), DEVICE. */
+int framrir_forward_multirate(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                              const double* mic_dev, const double* src_dev, const double* r_dev, float* inter_dev,
+                              float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The stages of framrir_forward_multirate after the render: the high-pass of
+ * the intermediate signal inter_dev[0 .. mr_floats) (scratch in inter_dev
+ * [mr_floats .. 2 mr_floats)) and the decimation into out_dev.  Arguments and
+ * errors as for framrir_forward_multirate. */
+int framrir_multirate_filter(const framrir_plan* plan, const void* desc_dev, float* inter_dev, float* out_dev,
+                             void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Initialises the counters at the start of a render / backward workspace
  * (enqueues one small kernel; no host synchronisation). */

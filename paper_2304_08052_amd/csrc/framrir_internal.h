@@ -40,6 +40,14 @@ struct DescHeader {
     int64_t early_floats;      // floats of the packed early-reverberation windows
     int32_t max_early;         // longest early window (samples)
     int32_t max_room_chan;     // largest n_src * n_mic of a room
+    // multi-rate plans (Sec. II): the render works at r_l fs into an
+    // intermediate buffer of mr_floats; out_floats is the output at fs
+    int32_t multirate;
+    int32_t max_chunks;        // high-pass chunks per channel, at most
+    int64_t mr_floats;
+    int64_t n_chunks;          // high-pass chunks of the batch
+    int32_t max_out_tiles;     // decimation tiles per channel, at most
+    int32_t max_rl;
 };
 
 struct RoomDesc {
@@ -54,7 +62,31 @@ struct RoomDesc {
     double fs, c;              // sample rate and speed of sound (early window index)
     int64_t early_off;         // first float of the room's early windows
     int32_t early_pre, early_post;   // ceil(6 fs / 1000), ceil(50 fs / 1000) (Eq. 9)
+    // multi-rate plans only (hr = 0 otherwise).  T, fs_over_c and out_off
+    // above then describe the intermediate signal at r_l fs.
+    double hr;                 // r_h fs (exact)
+    double lm1;                // L - 1, L = ceil(T60 r_h fs)
+    double rl, rh;             // r_l, r_h
+    double hp_b0, hp_a1, hp_a2;   // 80 Hz Butterworth high-pass: b = b0 (1, -2, 1), a = (1, a1, a2)
+    double phi[4];             // state transition of the high-pass over one chunk (row-major)
+    int64_t out2_off;          // first float of the room in the output at fs
+    int64_t chunk0;            // first high-pass chunk of the room
+    int32_t T_out;             // ceil(T60 fs)
+    int32_t n_chunks;          // high-pass chunks per channel
 };
+
+constexpr int kHpChunk = 256;         // intermediate samples per high-pass chunk
+constexpr int kHpBatch = 32;          // samples a high-pass thread loads at once
+constexpr int kDecThreads = 64;       // threads per decimation block
+constexpr int kDecPerThread = 8;      // consecutive outputs per decimation thread
+constexpr int kDecOut = kDecThreads * kDecPerThread;   // output samples per decimation tile
+constexpr int kMaxRl = 12;            // largest r_l a multi-rate plan accepts
+constexpr int kHpBasisStride = 2 * kHpChunk;   // doubles per room: unforced responses ha, hb
+// Decimation taps k[u] = P(u / r_l), stored phase-major per room: row q
+// (u = m r_l + q, 0 <= q < r_l) holds k at m = M0 .. M1, M1 = -M0 =
+// ceil(half / r_l) + 2 kDecPerThread (zero outside |u| <= half), so the taps
+// one super-step needs are consecutive floats.  Floats per room, widest r_l:
+constexpr int kDecTapStride = kMaxRl * (2 * (41 + 2 * kDecPerThread) + 1);
 
 struct SrcDesc {
     double d0, q, ct, rrmax;   // |src - centre|, c0T60 / d0, c0T60, RR_max (Eq. 5)

@@ -160,16 +160,34 @@ __device__ __forceinline__ float sinc_small(float x) {
 
 // Per-pair setup: D = |pos - mic| and t = D fs / c in FP64 (delays up to
 // ~6e4 samples must stay accurate to ~1e-7 samples), then FP32 quantities.
+__device__ __forceinline__ Pair pair_from_delay(double t, double D, double dx, double dy, double dz, float amp);
+
 __device__ __forceinline__ Pair pair_setup(double px, double py, double pz, double mx, double my, double mz,
                                            double fs_over_c, float amp) {
-    Pair P;
     const double dx = px - mx, dy = py - my, dz = pz - mz;
     const double d2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
     // sqrt from the hardware reciprocal square root and one Newton step
     const double rs = __builtin_amdgcn_rsq(d2);
     const double y0 = d2 * rs;
     const double D = __builtin_fma(__builtin_fma(-y0, y0, d2), 0.5 * rs, y0);
-    const double t = D * fs_over_c;
+    return pair_from_delay(D * fs_over_c, D, dx, dy, dz, amp);
+}
+
+// The same pair on the paper's high-rate grid (Eq. 7): q = min(ceil(D / c0 *
+// r_h fs), L - 1) with D correctly rounded and one rounding per operation, so
+// the integer q is the one the plain definition gives; the pulse then sits at
+// t = q r_l / r_h intermediate samples (the r_h -> r_l down-sampling).
+__device__ __forceinline__ Pair pair_setup_high_rate(double px, double py, double pz, double mx, double my,
+                                                     double mz, double c0, double hr, double lm1, double rl,
+                                                     double rh, float amp) {
+    const double dx = px - mx, dy = py - my, dz = pz - mz;
+    const double D = sqrt_rn(dx * dx + dy * dy + dz * dz);
+    const double q = fmin(__builtin_ceil((D / c0) * hr), lm1);
+    return pair_from_delay((q * rl) / rh, D, dx, dy, dz, amp);
+}
+
+__device__ __forceinline__ Pair pair_from_delay(double t, double D, double dx, double dy, double dz, float amp) {
+    Pair P;
     const double kf = __builtin_floor(t + 0.5);
     P.k = static_cast<int>(kf);
     P.dl = static_cast<float>(t - kf);
@@ -357,6 +375,7 @@ struct ItemCtx {
     int64_t out_off, img_off;
     double fs_over_c, cx, cy, cz;
     double r, log2r;
+    double c0, hr, lm1, rl, rh;   // multi-rate plans: pulses on the high-rate grid (hr > 0)
     float margin;   // max |mic - centre| fs / c + 2 samples, for the tile test
     float rho;      // max |mic - centre| of the group (metres)
 };
@@ -380,6 +399,11 @@ __device__ __forceinline__ void load_item(const void* desc, int item, const doub
     c.cz = R->centre[2];
     c.r = r_in ? r_in[S->room] : R->r;
     c.log2r = log2(c.r);
+    c.c0 = R->c;
+    c.hr = R->hr;
+    c.lm1 = R->lm1;
+    c.rl = R->rl;
+    c.rh = R->rh;
     c.rowlen = c.w.len + 2 * kHalo;
     double mx = 0.0;
     for (int m = 0; m < c.w.n_mic; ++m) {
@@ -723,8 +747,12 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
                 ++m;
             }
             if (p < n_pairs) row = rows[j];   // prefetch the next pair's row
-            const Pair P = pair_setup(cur.x, cur.y, cur.z, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2],
-                                      c.fs_over_c, render_row_amp(cur.w));
+            const Pair P = c.hr > 0.0
+                               ? pair_setup_high_rate(cur.x, cur.y, cur.z, micq[3 * cm], micq[3 * cm + 1],
+                                                      micq[3 * cm + 2], c.c0, c.hr, c.lm1, c.rl, c.rh,
+                                                      render_row_amp(cur.w))
+                               : pair_setup(cur.x, cur.y, cur.z, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2],
+                                            c.fs_over_c, render_row_amp(cur.w));
             const int b0 = P.k + shift;
             if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
             const float S = P.S * scale;
@@ -1006,6 +1034,243 @@ __global__ void __launch_bounds__(256) early_kernel(const void* __restrict__ des
     }
 }
 
+// ---------------------------------------------------------------------------
+// Multi-rate chain after the render (Sec. II): 80 Hz high-pass at r_l fs, then
+// decimation by r_l.
+// ---------------------------------------------------------------------------
+// High-pass y[n] = b0 (x[n] - 2 x[n-1] + x[n-2]) - a1 y[n-1] - a2 y[n-2] (FP64)
+// over chunks of kHpChunk samples evaluated in parallel and exactly: every
+// chunk is first filtered from a zero state (its input history is known), the
+// true initial states are then carried from chunk to chunk through the
+// chunk's state transition phi, and each chunk adds the unforced response of
+// its initial state.  One wave per 64 consecutive chunks of a channel (lane =
+// chunk); batches of kHpBatch samples go through LDS, so that the global
+// loads and stores are whole 128-byte lines while each lane runs its chunk's
+// recurrence.  Blocks: (chunks / 64, rooms, channels of the room).
+
+// Coalesced move of one batch (samples off .. off + kHpBatch of 64 chunks)
+// between global memory g (the channel's first sample) and buf[chunk][i].
+template <bool LOAD>
+__device__ __forceinline__ void hp_batch_move(float* __restrict__ g, float (*buf)[kHpBatch + 1], int kbase, int off,
+                                              const RoomDesc* R) {
+    const int lane = threadIdx.x;
+#pragma unroll 4
+    for (int it = 0; it < kHpBatch; ++it) {
+        const int e = it * 64 + lane;
+        const int c = e / kHpBatch, i = e % kHpBatch;
+        const int kc = kbase + c;
+        const int n = kc * kHpChunk + off + i;
+        const bool ok = kc < R->n_chunks && n < R->T;
+        if constexpr (LOAD) {
+            buf[c][i] = ok ? g[n] : 0.0f;
+        } else {
+            if (ok) g[n] = buf[c][i];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) hp_zero_state_kernel(const void* __restrict__ desc,
+                                                           const float* __restrict__ x, float* __restrict__ y,
+                                                           double* __restrict__ zend) {
+    __shared__ float buf[64][kHpBatch + 1];
+    const DescHeader* H = hdr(desc);
+    const int lane = threadIdx.x;
+    for (int b = blockIdx.y; b < H->n_rooms; b += gridDim.y) {
+        const RoomDesc* R = rooms(desc) + b;
+        const int kbase = blockIdx.x * 64;
+        if (kbase >= R->n_chunks) continue;
+        for (int local = blockIdx.z; local < R->n_src * R->n_mic; local += gridDim.z) {
+            const int64_t base = R->out_off + static_cast<int64_t>(local) * R->T;
+            const int k = kbase + lane;
+            const bool live = k < R->n_chunks;
+            const int s0 = k * kHpChunk, s1 = min(R->T, s0 + kHpChunk);
+            const double b0 = R->hp_b0, a1 = R->hp_a1, a2 = R->hp_a2;
+            double x1 = 0.0, x2 = 0.0, y1 = 0.0, y2 = 0.0;
+            if (live && s0 >= 1) x1 = x[base + s0 - 1];
+            if (live && s0 >= 2) x2 = x[base + s0 - 2];
+            for (int off = 0; off < kHpChunk; off += kHpBatch) {
+                __syncthreads();
+                hp_batch_move<true>(const_cast<float*>(x) + base, buf, kbase, off, R);
+                __syncthreads();
+                if (live) {
+                    for (int i = 0; i < kHpBatch && s0 + off + i < s1; ++i) {
+                        const double xn = buf[lane][i];
+                        const double yn = b0 * ((xn - 2.0 * x1) + x2) - a1 * y1 - a2 * y2;
+                        buf[lane][i] = static_cast<float>(yn);
+                        x2 = x1;
+                        x1 = xn;
+                        y2 = y1;
+                        y1 = yn;
+                    }
+                }
+                __syncthreads();
+                hp_batch_move<false>(y + base, buf, kbase, off, R);
+            }
+            if (live) {
+                const int64_t ci = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks + k;
+                zend[2 * ci] = y1;
+                zend[2 * ci + 1] = y2;
+            }
+        }
+    }
+}
+
+// Per room: the unforced responses ha, hb of the high-pass over one chunk
+// from the states (y[-1], y[-2]) = (1, 0) and (0, 1), and the phase-major
+// decimation taps; then the initial state (y[s-1], y[s-2]) of every chunk,
+// one thread per channel, chunk after chunk:
+// end(k) = zero-state end(k) + phi init(k).
+
+__global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ desc, const double* __restrict__ zend,
+                                                      double* __restrict__ init, double* __restrict__ basis,
+                                                      float* __restrict__ dec_taps) {
+    const DescHeader* H = hdr(desc);
+    for (int b = blockIdx.x; b < H->n_rooms; b += gridDim.x) {
+        const RoomDesc* R = rooms(desc) + b;
+        const double a1 = R->hp_a1, a2 = R->hp_a2;
+        if (threadIdx.x < 2) {   // lane 0: ha, lane 1: hb
+            double h1 = threadIdx.x == 0 ? 1.0 : 0.0, h2 = threadIdx.x == 0 ? 0.0 : 1.0;
+            double* out = basis + static_cast<int64_t>(b) * kHpBasisStride + threadIdx.x * kHpChunk;
+            for (int i = 0; i < kHpChunk; ++i) {
+                const double h = -a1 * h1 - a2 * h2;
+                out[i] = h;
+                h2 = h1;
+                h1 = h;
+            }
+        }
+        const int rl = static_cast<int>(R->rl);
+        const int half = static_cast<int>(__builtin_ceil(40.5 * rl)) - 1;
+        const int m1 = (half + rl - 1) / rl + 2 * kDecPerThread, len = 2 * m1 + 1;
+        float* taps = dec_taps + static_cast<int64_t>(b) * kDecTapStride;
+        for (int i = threadIdx.x; i < rl * len; i += blockDim.x) {
+            const int q = i / len, m = i % len - m1;
+            const int u = m * rl + q;
+            float v = 0.0f;
+            if (u >= -half && u <= half) {   // P(u / r_l) in FP64, then rounded
+                const double xv = static_cast<double>(u) / rl;
+                double sp, cp, sw, cw;
+                sincospi_d(xv, &sp, &cp);
+                sincospi_d(2.0 * xv / 81.0, &sw, &cw);
+                const double sinc = u == 0 ? 1.0 : sp / (3.141592653589793 * xv);
+                v = static_cast<float>(sinc * 0.5 * (1.0 + cw));
+            }
+            taps[i] = v;
+        }
+        const double p0 = R->phi[0], p1 = R->phi[1], p2 = R->phi[2], p3 = R->phi[3];
+        for (int local = threadIdx.x; local < R->n_src * R->n_mic; local += blockDim.x) {
+            const int64_t c0 = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks;
+            double s0 = 0.0, s1 = 0.0;
+            for (int k = 0; k < R->n_chunks; ++k) {
+                init[2 * (c0 + k)] = s0;
+                init[2 * (c0 + k) + 1] = s1;
+                const double n0 = zend[2 * (c0 + k)] + (p0 * s0 + p1 * s1);
+                const double n1 = zend[2 * (c0 + k) + 1] + (p2 * s0 + p3 * s1);
+                s0 = n0;
+                s1 = n1;
+            }
+        }
+    }
+}
+
+
+// Decimation by r_l (Sec. II): out[n] = sum_j x[j] P((n r_l - j) / r_l), the
+// 81-tap Hann-windowed sinc in units of fs.  x is the high-passed signal: the
+// zero-state chunks y0 plus, per chunk k >= 1, init(k) . (ha, hb), added
+// while the tile's input span is staged into LDS (zero outside [0, T_l)).  One
+// block per (tile of kDecOut outputs, room, channel); each thread R
+// consecutive outputs.  With w = r r_l - u, output r reads span[R tid r_l +
+// half + w] with tap k[r r_l - w]: for fixed w every output reads the same
+// input.  The walk goes phase by phase (w mod r_l), R steps at a time: R
+// inputs from LDS and the 2R - 1 taps, consecutive in the phase-major table
+// (uniform: one wide scalar load), per R x R FMAs.
+__global__ void __launch_bounds__(kDecThreads) decimate_kernel(const void* __restrict__ desc,
+                                                               const float* __restrict__ y0,
+                                                               const double* __restrict__ init,
+                                                               const double* __restrict__ basis,
+                                                               const float* __restrict__ dec_taps,
+                                                               float* __restrict__ out) {
+    constexpr int NR = kDecPerThread, UNR = 8;
+    extern __shared__ float span[];
+    const DescHeader* H = hdr(desc);
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.y; b < H->n_rooms; b += gridDim.y) {
+        const RoomDesc* R = rooms(desc) + b;
+        const int rl = static_cast<int>(R->rl);
+        const int half = static_cast<int>(__builtin_ceil(40.5 * rl)) - 1;
+        const int m1 = (half + rl - 1) / rl + 2 * NR, len = 2 * m1 + 1;
+        const float* taps = dec_taps + static_cast<int64_t>(b) * kDecTapStride;
+        const double* ha = basis + static_cast<int64_t>(b) * kHpBasisStride;
+        const double* hb = ha + kHpChunk;
+        const int n_tiles = (R->T_out + kDecOut - 1) / kDecOut;
+        for (int local = blockIdx.z; local < R->n_src * R->n_mic; local += gridDim.z) {
+            const float* xc = y0 + R->out_off + static_cast<int64_t>(local) * R->T;
+            const double* ic = init + 2 * (R->chunk0 + static_cast<int64_t>(local) * R->n_chunks);
+            for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+                __syncthreads();
+                const int n0 = tile * kDecOut;
+                const int64_t jb = static_cast<int64_t>(n0) * rl - half;   // input index of span[0]
+                const int span_len = (kDecOut - 1) * rl + 2 * half + 1;
+                for (int i0 = tid; i0 < span_len; i0 += UNR * kDecThreads) {
+                    double v[UNR];
+#pragma unroll
+                    for (int e = 0; e < UNR; ++e) {   // all loads first: one latency per UNR samples
+                        const int64_t j = jb + i0 + e * kDecThreads;
+                        const bool in = i0 + e * kDecThreads < span_len && j >= 0 && j < R->T;
+                        v[e] = 0.0;
+                        if (in) {
+                            const int k = static_cast<int>(j / kHpChunk), o = static_cast<int>(j % kHpChunk);
+                            v[e] = xc[j];
+                            if (k > 0) v[e] += ic[2 * k] * ha[o] + ic[2 * k + 1] * hb[o];
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < UNR; ++e)
+                        if (i0 + e * kDecThreads < span_len) span[i0 + e * kDecThreads] = static_cast<float>(v[e]);
+                }
+                __syncthreads();
+                float acc[NR];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r] = 0.0f;
+                const int sbase = NR * tid * rl + half;
+                const int w_hi = (NR - 1) * rl + half;   // w runs over [-half, w_hi]
+                for (int p = 0; p < rl; ++p) {
+                    // w = a r_l + p; the tap of output r, k[(r - a) r_l - p], is row
+                    // q = (r_l - p) mod r_l, column m = r - a - (p > 0) of the table
+                    int w = -half + (p + half) % rl;
+                    int a = (w - p) / rl;
+                    const int sh = p > 0 ? 1 : 0;
+                    const float* tq = taps + ((rl - p) % rl) * len + m1;   // tq[m]
+                    for (; w + (NR - 1) * rl <= w_hi; w += NR * rl, a += NR) {
+                        // inputs at w + s r_l (s < NR); output r takes the tap at
+                        // column (r - s) - a - sh = m0 + (r - s + NR - 1)
+                        const int m0 = -(NR - 1) - a - sh;
+                        float xs[NR], tt[2 * NR - 1];
+#pragma unroll
+                        for (int s2 = 0; s2 < NR; ++s2) xs[s2] = span[sbase + w + s2 * rl];
+#pragma unroll
+                        for (int d = 0; d < 2 * NR - 1; ++d) tt[d] = tq[m0 + d];
+#pragma unroll
+                        for (int s2 = 0; s2 < NR; ++s2)
+#pragma unroll
+                            for (int r = 0; r < NR; ++r) acc[r] = __builtin_fmaf(tt[r - s2 + NR - 1], xs[s2], acc[r]);
+                    }
+                    for (; w <= w_hi; w += rl, ++a) {   // the phase's last steps
+                        const float xv = span[sbase + w];
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) acc[r] = __builtin_fmaf(tq[r - a - sh], xv, acc[r]);
+                    }
+                }
+                float* o = out + R->out2_off + static_cast<int64_t>(local) * R->T_out;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int n = n0 + NR * tid + r;
+                    if (n < R->T_out) o[n] = acc[r];
+                }
+            }
+        }
+    }
+}
+
 __global__ void zero_counters_kernel(int* counters) {
     if (threadIdx.x < 2) counters[threadIdx.x] = 0;
 }
@@ -1152,6 +1417,8 @@ int check_render_args(const framrir_plan* plan, const void* desc_dev, const doub
 extern "C" int framrir_prepare(const framrir_plan* plan, const void* desc_dev, double* table_dev,
                                const double* mic_dev, const double* src_dev, const double* r_dev, int draw,
                                void* ws_dev, size_t ws_bytes, void* stream) {
+    if (plan && plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
     int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, table_dev, ws_dev, ws_bytes,
                                plan ? plan->ws_bytes : 0);
     if (rc) return rc;
@@ -1162,6 +1429,8 @@ extern "C" int framrir_prepare(const framrir_plan* plan, const void* desc_dev, d
 extern "C" int framrir_render_prepared(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
                                        const double* mic_dev, const double* src_dev, const double* r_dev,
                                        float* out_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (plan && plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
     int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
                                plan ? plan->ws_bytes : 0);
     if (rc) return rc;
@@ -1192,6 +1461,8 @@ extern "C" int framrir_render_backward_prepared(const framrir_plan* plan, const 
                                                 const double* mic_dev, const double* r_dev,
                                                 const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
                                                 float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (plan && plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
     if (!plan || !desc_dev || !mic_dev || !grad_out_dev || !ws_dev)
         return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
     if (!aligned(desc_dev, 256) || !aligned(ws_dev, 256) || !aligned(grad_out_dev, 4))
@@ -1225,6 +1496,8 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
                                        const double* mic_dev, const double* src_dev, const double* r_dev,
                                        const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
                                        float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (plan && plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
     int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, grad_out_dev, ws_dev, ws_bytes,
                                plan ? plan->ws_bwd_bytes : 0);
     if (rc) return rc;
@@ -1238,6 +1511,8 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
 extern "C" int framrir_early(const framrir_plan* plan, const void* desc_dev, const double* mic_dev,
                              const double* src_dev, const float* out_dev, float* early_dev, int32_t* start_dev,
                              void* stream) {
+    if (plan && plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
     if (!plan || !desc_dev || !mic_dev || !src_dev || !out_dev || !early_dev)
         return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
     if (!aligned(desc_dev, 256)) return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned descriptor");
@@ -1249,6 +1524,62 @@ extern "C" int framrir_early(const framrir_plan* plan, const void* desc_dev, con
     hipLaunchKernelGGL(early_kernel, dim3(gx, gy, gz), dim3(256), 0, static_cast<hipStream_t>(stream), desc_dev,
                        mic_dev, src_dev, out_dev, early_dev, start_dev);
     return check_launch("early_kernel");
+}
+
+// LDS floats of decimate_kernel for a given r_l (the input span).
+int dec_lds_floats(int rl) {
+    const int half = static_cast<int>(std::ceil(40.5 * rl)) - 1;
+    return (kDecOut - 1) * rl + 2 * half + 1;
+}
+
+extern "C" int framrir_multirate_filter(const framrir_plan* plan, const void* desc_dev, float* inter_dev,
+                                        float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+extern "C" int framrir_forward_multirate(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                                         const double* mic_dev, const double* src_dev, const double* r_dev,
+                                         float* inter_dev, float* out_dev, void* ws_dev, size_t ws_bytes,
+                                         void* stream) {
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_mr_bytes : 0);
+    if (rc) return rc;
+    const DescHeader& H = plan->header;
+    if (!H.multirate) return fr_fail(FRAMRIR_E_UNSUPPORTED, "not a multi-rate plan (FRAMRIR_FLAG_MULTIRATE)");
+    if (!inter_dev || !aligned(inter_dev, 4)) return fr_fail(FRAMRIR_E_INVALID_ARG, "inter_dev NULL or misaligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = launch_prepare(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, ws_dev, st, true))) return rc;
+    if ((rc = launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, inter_dev, ws_dev, st))) return rc;
+    return framrir_multirate_filter(plan, desc_dev, inter_dev, out_dev, ws_dev, ws_bytes, stream);
+}
+
+extern "C" int framrir_multirate_filter(const framrir_plan* plan, const void* desc_dev, float* inter_dev,
+                                        float* out_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (!plan || !desc_dev || !inter_dev || !out_dev || !ws_dev) return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
+    if (!aligned(desc_dev, 256) || !aligned(ws_dev, 256) || !aligned(inter_dev, 4) || !aligned(out_dev, 4))
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned buffer");
+    const DescHeader& H = plan->header;
+    if (!H.multirate) return fr_fail(FRAMRIR_E_UNSUPPORTED, "not a multi-rate plan (FRAMRIR_FLAG_MULTIRATE)");
+    if (static_cast<int64_t>(ws_bytes) < plan->ws_mr_bytes)
+        return fr_fail(FRAMRIR_E_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes,
+                       static_cast<long long>(plan->ws_mr_bytes));
+    int rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* filt = inter_dev + H.mr_floats;
+    double* zend = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + plan->ws_zend_off);
+    double* init = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + plan->ws_init_off);
+    const unsigned gy = static_cast<unsigned>(std::min(H.n_rooms, 65535));
+    const unsigned gz = static_cast<unsigned>(std::min(H.max_room_chan, 65535));
+    const unsigned gc = static_cast<unsigned>((H.max_chunks + 63) / 64);
+    hipLaunchKernelGGL(hp_zero_state_kernel, dim3(gc, gy, gz), dim3(64), 0, st, desc_dev, inter_dev, filt, zend);
+    if ((rc = check_launch("hp_zero_state_kernel"))) return rc;
+    double* basis = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + plan->ws_basis_off);
+    float* dec_taps = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + plan->ws_taps_off);
+    hipLaunchKernelGGL(hp_carry_kernel, dim3(gy), dim3(64), 0, st, desc_dev, zend, init, basis, dec_taps);
+    if ((rc = check_launch("hp_carry_kernel"))) return rc;
+    const int lds = 4 * dec_lds_floats(H.max_rl);
+    if (int rc2 = allow_lds<decimate_kernel>()) return rc2;
+    hipLaunchKernelGGL(decimate_kernel, dim3(static_cast<unsigned>(std::min(H.max_out_tiles, 65535)), gy, gz),
+                       dim3(kDecThreads), lds, st, desc_dev, filt, init, basis, dec_taps, out_dev);
+    return check_launch("decimate_kernel");
 }
 
 extern "C" int framrir_workspace_init(void* ws_dev, size_t ws_bytes, void* stream) {

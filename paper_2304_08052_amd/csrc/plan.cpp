@@ -121,7 +121,9 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     if (!(prm.img_lo >= 0 && prm.img_lo <= prm.img_hi && prm.img_hi <= 65535))
         return fr_fail(FRAMRIR_E_RANGE, "need 0 <= img_lo <= img_hi <= 65535 (%d, %d)", prm.img_lo, prm.img_hi);
     if (prm.taps != FRAMRIR_TAPS) return fr_fail(FRAMRIR_E_UNSUPPORTED, "taps must be 81 (got %d)", prm.taps);
-    if (prm.flags != 0u) return fr_fail(FRAMRIR_E_UNSUPPORTED, "flags must be 0");
+    if ((prm.flags & ~FRAMRIR_FLAG_MULTIRATE) != 0u)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "unknown flags 0x%x", prm.flags);
+    const bool multirate = (prm.flags & FRAMRIR_FLAG_MULTIRATE) != 0u;
 
     // ---- launch shape
     if (launch.wg_threads < 64 || launch.wg_threads > 1024 || launch.wg_threads % 64 != 0)
@@ -148,8 +150,8 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     std::vector<RoomDesc>& rd = plan->rooms;
     std::vector<SrcDesc>& sd = plan->srcs;
     rd.resize(n_rooms);
-    int64_t out_off = 0, img_off = 0, early_off = 0;
-    int32_t chan_row = 0, max_early = 0, max_room_chan = 0;
+    int64_t out_off = 0, img_off = 0, early_off = 0, out2_off = 0, chunk_row = 0;
+    int32_t chan_row = 0, max_early = 0, max_room_chan = 0, max_chunks = 0, max_out_tiles = 0, max_rl = 0;
     int32_t src_row = 0, mic_row = 0, max_img = 0, max_T = 0;
 
     for (int32_t b = 0; b < n_rooms; ++b) {
@@ -177,6 +179,31 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
             return fr_fail(FRAMRIR_E_RANGE, "room %d: T = ceil(T60 fs) out of range", b);
         }
         const int32_t T = static_cast<int32_t>(t_samples);
+        // the render's rate and length: fs and T, or r_l fs and T_l for the
+        // paper-literal multi-rate rendering (Sec. II, Sec. III-D)
+        double fs_r = rm.fs, hr = 0.0, lm1 = 0.0;
+        int32_t T_r = T, rh = 0, rl = 0;
+        if (multirate) {
+            const double rhd = std::floor(1.0e6 / rm.fs);
+            rh = rhd >= 1.0 && rhd < 2147483647.0 ? static_cast<int32_t>(rhd) : 0;
+            rl = 0;
+            while (static_cast<int64_t>(rl + 1) * (rl + 1) <= rh) ++rl;   // floor(sqrt(r_h)) in integers
+            if (!(rl > 1 && rl <= kMaxRl)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_RANGE, "room %d: multi-rate needs 1 < r_l <= %d (fs = %g gives r_h = %d)", b,
+                               kMaxRl, rm.fs, rh);
+            }
+            hr = rh * rm.fs;
+            const double big_l = std::ceil(rm.rt60 * hr);
+            fs_r = rl * rm.fs;
+            const double tl = std::ceil(rm.rt60 * fs_r);
+            if (!(big_l >= 1.0 && big_l <= 9007199254740992.0 && tl >= 1.0 && tl <= 2147483647.0 - 256.0)) {
+                delete plan;
+                return fr_fail(FRAMRIR_E_RANGE, "room %d: multi-rate lengths out of range", b);
+            }
+            lm1 = big_l - 1.0;
+            T_r = static_cast<int32_t>(tl);
+        }
         double r;
         if (std::isnan(rm.r_override)) {
             r = eyring_r(rm.size, rm.rt60);
@@ -207,13 +234,15 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         const double nm = static_cast<double>(rm.n_mic);
         RoomDesc& R = rd[b];
         std::memset(&R, 0, sizeof(R));
-        R.fs_over_c = rm.fs / rm.c;
+        R.fs_over_c = fs_r / rm.c;
         R.r = r;
         R.centre[0] = cx / nm;
         R.centre[1] = cy / nm;
         R.centre[2] = cz / nm;
         R.out_off = out_off;
-        R.T = T;
+        R.T = T_r;
+        R.T_out = T;
+        R.out2_off = multirate ? out2_off : out_off;
         R.n_src = rm.n_src;
         R.n_mic = rm.n_mic;
         R.src0 = src_row;
@@ -224,6 +253,40 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         R.early_off = early_off;
         R.early_pre = static_cast<int32_t>(std::ceil(6.0 * rm.fs / 1000.0));
         R.early_post = static_cast<int32_t>(std::ceil(50.0 * rm.fs / 1000.0));
+        if (multirate) {
+            R.hr = hr;
+            R.lm1 = lm1;
+            R.rl = rl;
+            R.rh = rh;
+            // second-order Butterworth high-pass, bilinear with the cut-off
+            // prewarped to 80 Hz at r_l fs: b = b0 (1, -2, 1), a = (1, a1, a2)
+            const double k = std::tan(M_PI * 80.0 / fs_r);
+            const double norm = 1.0 + std::sqrt(2.0) * k + k * k;
+            R.hp_b0 = 1.0 / norm;
+            R.hp_a1 = 2.0 * (k * k - 1.0) / norm;
+            R.hp_a2 = (1.0 - std::sqrt(2.0) * k + k * k) / norm;
+            // phi = M^kHpChunk, M = [[-a1, -a2], [1, 0]] maps (y[n-1], y[n-2])
+            // of the unforced recurrence to (y[n], y[n-1])
+            double m[4] = {-R.hp_a1, -R.hp_a2, 1.0, 0.0}, acc[4] = {1.0, 0.0, 0.0, 1.0};
+            for (int e = kHpChunk; e > 0; e >>= 1) {
+                double t[4];
+                if (e & 1) {
+                    t[0] = acc[0] * m[0] + acc[1] * m[2];
+                    t[1] = acc[0] * m[1] + acc[1] * m[3];
+                    t[2] = acc[2] * m[0] + acc[3] * m[2];
+                    t[3] = acc[2] * m[1] + acc[3] * m[3];
+                    std::memcpy(acc, t, sizeof(t));
+                }
+                t[0] = m[0] * m[0] + m[1] * m[2];
+                t[1] = m[0] * m[1] + m[1] * m[3];
+                t[2] = m[2] * m[0] + m[3] * m[2];
+                t[3] = m[2] * m[1] + m[3] * m[3];
+                std::memcpy(m, t, sizeof(t));
+            }
+            std::memcpy(R.phi, acc, sizeof(acc));
+            R.n_chunks = (T_r + kHpChunk - 1) / kHpChunk;
+            R.chunk0 = chunk_row;
+        }
         const double ct = rm.c * rm.rt60;
         const double log10_r = std::log10(r);
         const double log10_ct = std::log10(ct);
@@ -283,15 +346,22 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
             max_img = std::max(max_img, S.n_img);
             sd.push_back(S);
         }
-        out_off += static_cast<int64_t>(rm.n_src) * rm.n_mic * T;
+        out_off += static_cast<int64_t>(rm.n_src) * rm.n_mic * T_r;
         const int32_t n_chan_room = rm.n_src * rm.n_mic;
+        if (multirate) {
+            out2_off += static_cast<int64_t>(n_chan_room) * T;
+            chunk_row += static_cast<int64_t>(n_chan_room) * R.n_chunks;
+            max_chunks = std::max(max_chunks, R.n_chunks);
+            max_out_tiles = std::max(max_out_tiles, (T + kDecOut - 1) / kDecOut);
+            max_rl = std::max(max_rl, rl);
+        }
         early_off += static_cast<int64_t>(n_chan_room) * (R.early_pre + R.early_post + 1);
         chan_row += n_chan_room;
         max_early = std::max(max_early, R.early_pre + R.early_post + 1);
         max_room_chan = std::max(max_room_chan, n_chan_room);
         src_row += rm.n_src;
         mic_row += rm.n_mic;
-        max_T = std::max(max_T, T);
+        max_T = std::max(max_T, T_r);
     }
 
     // ---- work items: per source, microphone groups x time tiles
@@ -369,6 +439,13 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     H.tau_code = tau_code;
     H.max_img = max_img;
     H.max_T = max_T;
+    H.multirate = multirate ? 1 : 0;
+    H.mr_floats = multirate ? out_off : 0;
+    if (multirate) H.out_floats = out2_off;
+    H.n_chunks = chunk_row;
+    H.max_chunks = max_chunks;
+    H.max_out_tiles = max_out_tiles;
+    H.max_rl = max_rl;
     H.n_chan = chan_row;
     H.early_floats = early_off;
     H.max_early = max_early;
@@ -397,6 +474,14 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     plan->ws_bytes = align(plan->ws_rows_off + static_cast<int64_t>(4 * sizeof(double)) * img_off);
     plan->ws_part_off = plan->ws_bytes;
     plan->ws_bwd_bytes = plan->ws_part_off + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
+    // multi-rate: per high-pass chunk its zero-state end (2 doubles) and its
+    // initial state (2 doubles)
+    plan->ws_zend_off = align(plan->ws_bytes);
+    plan->ws_init_off = align(plan->ws_zend_off + 16 * chunk_row);
+    plan->ws_basis_off = align(plan->ws_init_off + 16 * chunk_row);
+    plan->ws_taps_off = align(plan->ws_basis_off + static_cast<int64_t>(sizeof(double)) * kHpBasisStride * n_rooms);
+    plan->ws_mr_bytes =
+        multirate ? align(plan->ws_taps_off + static_cast<int64_t>(sizeof(float)) * kDecTapStride * n_rooms) : 0;
     int32_t grid = launch.grid_wgs;
     if (grid == 0) {
         const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + kStaticLdsBytes);
@@ -425,6 +510,9 @@ extern "C" int framrir_plan_get_info(const framrir_plan* plan, framrir_plan_info
     info->ws_bwd_bytes = plan->ws_bwd_bytes;
     info->max_T = H.max_T;
     info->max_img = H.max_img;
+    info->multirate = H.multirate;
+    info->mr_floats = H.mr_floats;
+    info->ws_mr_bytes = plan->ws_mr_bytes;
     info->n_chan = H.n_chan;
     info->early_floats = H.early_floats;
     return FRAMRIR_OK;
@@ -450,8 +538,8 @@ extern "C" int framrir_plan_get_arrays(const framrir_plan* plan, int32_t* T, int
     if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "plan is NULL");
     const DescHeader& H = plan->header;
     for (int32_t b = 0; b < H.n_rooms; ++b) {
-        if (T) T[b] = plan->rooms[b].T;
-        if (out_off) out_off[b] = plan->rooms[b].out_off;
+        if (T) T[b] = plan->rooms[b].T_out;
+        if (out_off) out_off[b] = plan->rooms[b].out2_off;
         if (r) r[b] = plan->rooms[b].r;
     }
     if (out_off) out_off[H.n_rooms] = H.out_floats;

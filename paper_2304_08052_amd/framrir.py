@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libframrir.so")
 
 FRAMRIR_TAPS = 81
+FRAMRIR_FLAG_MULTIRATE = 1
 
 
 class FramrirError(RuntimeError):
@@ -44,7 +45,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_items", ctypes.c_int32), ("n_img", ctypes.c_int64), ("out_floats", ctypes.c_int64),
                 ("desc_bytes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64), ("ws_bwd_bytes", ctypes.c_int64),
                 ("max_T", ctypes.c_int32), ("max_img", ctypes.c_int32), ("early_floats", ctypes.c_int64),
-                ("n_chan", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_chan", ctypes.c_int32), ("multirate", ctypes.c_int32), ("mr_floats", ctypes.c_int64),
+                ("ws_mr_bytes", ctypes.c_int64)]
 
 
 DEFAULT_PARAMS = dict(alpha=0.25, beta=1.0, a=-2.0, b=2.0, tau=0.25, img_lo=1024, img_hi=4096)
@@ -69,6 +71,8 @@ EXPORTS = {
     "framrir_workspace_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_plan_get_early": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "framrir_early": (ctypes.c_int, [ctypes.c_void_p] * 8),
+    "framrir_forward_multirate": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_multirate_filter": (ctypes.c_int, [ctypes.c_void_p] * 5 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_host_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64]),
@@ -127,8 +131,10 @@ class Plan:
     batch: dict with size (B,3), rt60, fs, c, r_override, seed, n_src, n_mic,
     src (sum n_src, 3), mic (sum n_mic, 3) -- see workloads.py."""
 
-    def __init__(self, batch, params=None, launch=None, device="cuda"):
-        """device="cpu" plans and keeps the blob in host memory (no GPU calls)."""
+    def __init__(self, batch, params=None, launch=None, device="cuda", multirate=False):
+        """device="cpu" plans and keeps the blob in host memory (no GPU calls).
+        multirate=True plans the paper-literal multi-rate rendering
+        (forward_multirate only)."""
         import torch
         L = lib()
         prm = dict(DEFAULT_PARAMS, **(params or {}))
@@ -149,7 +155,7 @@ class Plan:
         self.src = np.ascontiguousarray(batch["src"], dtype=np.float64)
         self.mic = np.ascontiguousarray(batch["mic"], dtype=np.float64)
         p = Params(prm["alpha"], prm["beta"], prm["a"], prm["b"], prm["tau"], prm["img_lo"], prm["img_hi"],
-                   FRAMRIR_TAPS, 0)
+                   FRAMRIR_TAPS, FRAMRIR_FLAG_MULTIRATE if multirate else 0)
         la = Launch(lau["lds_bytes"], lau["wg_threads"], lau["grid_wgs"], lau["max_mic_group"],
                     lau["waves_per_simd"])
         handle = ctypes.c_void_p()
@@ -287,6 +293,35 @@ class Plan:
                                                  _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws),
                                                  ws.numel(), _stream(stream)))
         return gm, gs, gr
+
+    def forward_multirate(self, table=None, mic=None, src=None, r=None, inter=None, out=None, ws=None,
+                          stream=None, desc=None):
+        """framrir_forward_multirate: draws, the render at r_l fs on the high-rate
+        grid, the 80 Hz high-pass and the decimation to fs.  Returns
+        (out [out_floats], table, inter [2 mr_floats]: the intermediate signal
+        at r_l fs, then the high-pass scratch)."""
+        import torch
+        table = self.empty_table() if table is None else table
+        out = self.empty_out() if out is None else out
+        inter = torch.empty(2 * self.info.mr_floats, dtype=torch.float32, device=self.device) if inter is None \
+            else inter
+        ws = torch.zeros(self.info.ws_mr_bytes, dtype=torch.uint8, device=self.device) if ws is None else ws
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_forward_multirate(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                               _ptr(inter), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out, table, inter
+
+    def multirate_filter(self, inter, out=None, ws=None, stream=None, desc=None):
+        """framrir_multirate_filter: high-pass and decimation of inter[:mr_floats]."""
+        import torch
+        out = self.empty_out() if out is None else out
+        ws = torch.zeros(self.info.ws_mr_bytes, dtype=torch.uint8, device=self.device) if ws is None else ws
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_multirate_filter(self._h, _ptr(desc), _ptr(inter), _ptr(out), _ptr(ws), ws.numel(),
+                                              _stream(stream)))
+        return out
 
     def early(self, out, early=None, start=None, mic=None, src=None, stream=None, desc=None):
         """framrir_early: the Eq. 9 windows of rendered RIRs `out`; returns
