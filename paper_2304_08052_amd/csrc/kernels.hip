@@ -418,19 +418,30 @@ __device__ __forceinline__ void load_item(const void* desc, int item, const doub
 // ---------------------------------------------------------------------------
 // Render: fixed-point scale, preparation and the scatter kernel
 // ---------------------------------------------------------------------------
-// Fixed-point budget of the LDS accumulators: a bound on the sum of |tap|
-// over every pair of a source bounds every sample of its RIRs, since the
-// pulse never exceeds 1 in magnitude; the bound plus the per-add rounding
-// slack is mapped just below 2^31.
+// Fixed-point budget of the LDS accumulators.  A sample n of a source's RIR
+// at any microphone only receives pulses of images whose centre delay lies
+// within H = 43 + rho fs / c samples of n (half the pulse, plus the largest
+// microphone offset from the array centre, plus rounding slack), and each
+// adds at most r^g / D there, since the pulse never exceeds 1 in magnitude.
+// The bound is therefore the largest sum of those terms over any window of
+// delay bins an interval of 2H samples can touch (for a multi-rate room every
+// window that reaches the clamped end runs to the last bin, since delays past
+// the RIR length are clamped onto its last sample).  That bound plus the
+// per-add rounding slack is mapped just below 2^31; the accumulators add
+// modulo 2^32, so only each sample's final sum has to fit.
 constexpr float kFixedBudget = 2147483648.0f - 262144.0f;
 constexpr float kBoundMargin = 1.0001f;
+constexpr int kBoundBins = 256;                     // bins of 4 delay buckets
+constexpr int kBinShift = 2;
+static_assert(kBuckets == (kBoundBins << kBinShift) && kBoundBins % 64 == 0, "delay bins");
 
 // ---------------------------------------------------------------------------
 // Render preparation: one workgroup per source.
-//   - the fixed-point scale of the source: budget / sum_i max_m r^g_i / D_im,
-//     with D_im >= |pos_i - centre| - rho (rho = largest |mic - centre| of
-//     the room), rows inside that sphere using the exact nearest microphone;
-//     summed in a fixed order, so the scale is reproducible;
+//   - the fixed-point scale of the source: budget / the largest windowed sum
+//     of max_m r^g_i / D_im, with D_im >= |pos_i - centre| - rho (rho =
+//     largest |mic - centre| of the room), rows inside that sphere using the
+//     exact nearest microphone; per-wave bin sums combined in a fixed order,
+//     so the scale is reproducible;
 //   - a counting sort of the source's rows by centre delay into kBuckets
 //     buckets: bucket offsets, and the rows themselves stored in that order
 //     as render rows (position, amplitude r^g as FP32).  A time tile then
@@ -513,6 +524,7 @@ __device__ __forceinline__ int prep_account(const RoomDesc* R, const double4& v,
 // plus the direct path).
 constexpr int kPrepThreads = 512;
 constexpr int kPrepWaves = kPrepThreads / 64;
+static_assert(kBoundBins <= kPrepThreads, "one thread per delay bin");
 constexpr int kMaxImg = 65536;
 __host__ __device__ constexpr int prep_key_cap(int max_img) { return ((max_img < kKeyCap ? max_img : kKeyCap) + 1) & ~1; }
 __host__ __device__ constexpr int prep_dyn_lds(int max_img) { return 2 * prep_key_cap(max_img); }
@@ -529,6 +541,8 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
     constexpr int NT = kPrepThreads, NW = kPrepWaves, BPT = kBuckets / NT;
     extern __shared__ unsigned short keys[];             // key_cap
     __shared__ int hist[NW][kBuckets];                   // per-wave bucket counts, then per-wave cursors
+    __shared__ float tsum[NW][kBoundBins];               // per-wave bound terms per delay bin
+    __shared__ float bins[kBoundBins];
     __shared__ float red[NW];
     __shared__ int wsum[NW];
     __shared__ float s_rho;
@@ -539,6 +553,7 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
     const RoomDesc* R = rooms(desc) + S->room;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int k = tid; k < NW * kBuckets; k += NT) (&hist[0][0])[k] = 0;
+    for (int k = tid; k < NW * kBoundBins; k += NT) (&tsum[0][0])[k] = 0.0f;
     if (tid == 0) {
         s_rho = 0.0f;
         if (S->s_local == 0) room_done[S->room] = 0;   // completion count of the room's backward items
@@ -560,16 +575,15 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
     const int w0 = min(n, wave * per_wave), w1 = min(n, w0 + per_wave);
     __syncthreads();
     const float rhof = s_rho * 1.000001f + 1e-7f;
-    float bsum = 0.0f;
     // pass 1: rows (drawn and stored when DRAW), bound terms, buckets and the
-    // wave's bucket counts
+    // wave's bucket counts and bin sums
     auto count_run = [&](int i, bool valid, const double4& v) {
         if (valid) {
             float amp, term;
             const int key = prep_account(R, v, log2r, rhof, inv_w, mic, amp, term);
-            bsum += term;
             if (i < key_cap) keys[i] = static_cast<unsigned short>(key);
             atomicAdd(&hist[wave][key], 1);
+            atomicAdd(&tsum[wave][key >> kBinShift], term);
         }
     };
     if constexpr (DRAW) {
@@ -595,9 +609,12 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
                 if (c + 64 * k < w1) count_run(c + 64 * k + lane, c + 64 * k + lane < w1, v[k]);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off);
-    if (lane == 0) red[wave] = bsum;
     __syncthreads();
+    if (tid < kBoundBins) {   // bin totals, waves in a fixed order
+        float t = 0.0f;
+        for (int w = 0; w < NW; ++w) t += tsum[w][tid];
+        bins[tid] = t;
+    }
     // bucket totals, exclusive scan (BPT buckets per thread), then each
     // wave's cursor: the bucket's start plus the earlier waves' counts
     int tot[BPT], run = 0;
@@ -614,6 +631,20 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
+    if (tid < kBoundBins) {   // the largest window sum (bins now complete)
+        const float H = 43.0f + rhof * static_cast<float>(R->fs_over_c) * 1.0001f;
+        const float cw = (R->T + 256.0f) * (1.0f / kBoundBins);
+        const int len = min(kBoundBins, static_cast<int>(__builtin_ceilf(2.0f * H / cw)) + 4);
+        int end = min(kBoundBins, tid + len);
+        if (R->hr > 0.0) {   // multi-rate: windows that reach the clamped end run to the last bin
+            const int kc = (bucket_of(R->T - 2.0f * H - 4.0f, inv_w) >> kBinShift) - 1;
+            if (tid >= kc) end = kBoundBins;
+        }
+        float wsum_bins = 0.0f;
+        for (int k = tid; k < end; ++k) wsum_bins += bins[k];
+        for (int off = 32; off > 0; off >>= 1) wsum_bins = fmaxf(wsum_bins, __shfl_xor(wsum_bins, off));
+        if (lane == 0) red[wave] = wsum_bins;
+    }
     int base = incl - run;
     for (int w = 0; w < wave; ++w) base += wsum[w];
     int* bo = bucket_off + static_cast<int64_t>(s) * (kBuckets + 1);
@@ -629,14 +660,14 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
         }
         base += tot[j];
     }
+    if (tid == 0) bo[kBuckets] = n;
+    __syncthreads();
     if (tid == 0) {
-        bo[kBuckets] = n;
         float b = 0.0f;
-        for (int w = 0; w < NW; ++w) b += red[w];
+        for (int w = 0; w < kBoundBins / 64; ++w) b = fmaxf(b, red[w]);
         b *= kBoundMargin;
         src_scale[s] = (b > 0.0f && b < 3.0e38f) ? kFixedBudget / b : 0.0f;
     }
-    __syncthreads();
     // pass 2: each wave places its rows through its own cursors, runs of 64
     // in row order.  Only this wave touches its cursors, and one LDS atomic
     // instruction resolves its colliding lanes in a fixed order, so the

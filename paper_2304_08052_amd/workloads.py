@@ -166,6 +166,47 @@ def small_mixed(n_rooms=4, seed=7, fs_choices=(16000.0, 48000.0), rt60_range=(0.
     return _uca_rooms(n_rooms, rng, (1, 3), (1, 8), rt60_range, fs_choices, seed0=seed * 1000)
 
 
+def _explicit_room(d, size, rt60, fs, seed, srcs, mics, r=np.nan):
+    d["size"].append(list(size))
+    d["rt60"].append(rt60)
+    d["fs"].append(fs)
+    d["c"].append(SOUND_SPEED)
+    d["r_override"].append(r)
+    d["seed"].append(seed)
+    d["n_src"].append(len(srcs))
+    d["n_mic"].append(len(mics))
+    d["src"].extend([list(v) for v in srcs])
+    d["mic"].extend([list(v) for v in mics])
+
+
+def edge_cases():
+    """Rooms at the edges of the admitted inputs, in one batch:
+      0  64 microphones (the largest count), circular array of radius 0.2 m, 2 sources;
+      1  a source 1 cm from a microphone (near field, direct-path gain 100);
+      2  T60 4 ms at 16 kHz: a 64-sample RIR, shorter than the 81-tap pulse;
+      3  48 kHz, 13-microphone linear array (ragged microphone groups), 3 sources;
+      4  10 x 10 x 4 m room, T60 0.1 s, source 6 m away (direct path late in the RIR);
+      5  reflection coefficient 0.95 (near-rigid walls);
+      6  reflection coefficient 0.02 (near-anechoic walls)."""
+    d = _empty()
+    _explicit_room(d, (7.0, 6.0, 3.0), 0.3, 16000.0, 501,
+                   [(1.5, 1.2, 1.4), (5.6, 4.9, 2.1)], circular_array((3.5, 3.0, 1.5), 64, 0.2, 0.1))
+    _explicit_room(d, (4.0, 4.0, 3.0), 0.25, 16000.0, 502,
+                   [(2.01, 2.0, 1.5)], [(2.0, 2.0, 1.5), (2.05, 2.0, 1.5)])
+    _explicit_room(d, (3.0, 3.0, 2.5), 0.004, 16000.0, 503,
+                   [(1.3, 1.5, 1.2)], [(1.6, 1.5, 1.2)])
+    _explicit_room(d, (6.0, 5.0, 3.2), 0.2, 48000.0, 504,
+                   [(1.0, 1.0, 1.6), (4.8, 3.9, 1.1), (3.0, 4.2, 2.5)],
+                   linear_array((3.2, 2.1, 1.3), 13, 0.03, 0.7))
+    _explicit_room(d, (10.0, 10.0, 4.0), 0.1, 16000.0, 505,
+                   [(8.5, 5.0, 2.0)], [(2.5, 5.0, 2.0)])
+    _explicit_room(d, (5.0, 4.0, 3.0), 0.5, 16000.0, 506,
+                   [(1.0, 1.0, 1.0)], [(3.9, 2.8, 1.7), (3.95, 2.8, 1.7)], r=0.95)
+    _explicit_room(d, (5.0, 4.0, 3.0), 0.5, 16000.0, 507,
+                   [(1.0, 3.0, 2.0), (4.0, 1.0, 1.0)], [(2.5, 2.0, 1.5)], r=0.02)
+    return _finish(d)
+
+
 def upstream_grad(shape_total, seed=0):
     """Seeded N(0, 1) FP32 upstream gradient for backward benchmarks."""
     rng = np.random.default_rng([3000, seed])

@@ -64,9 +64,10 @@ def _edge_batch():
                 src=np.array([[2.0, 2.0, 1.5]]), mic=np.array([[2.2, 2.0, 1.5], [5.5, 4.5, 2.5]]))
 
 
-@pytest.mark.parametrize("which", ["small_mixed", "edges"])
+@pytest.mark.parametrize("which", ["small_mixed", "edges", "edge_cases"])
 def test_early_matches_oracle(which):
-    batch = W.small_mixed(6, seed=31) if which == "small_mixed" else _edge_batch()
+    batch = dict(small_mixed=lambda: W.small_mixed(6, seed=31), edges=_edge_batch,
+                 edge_cases=W.edge_cases)[which]()
     say(f"early windows {which}")
     plan, out, early, start = _run(batch)
     assert np.array_equal(start.astype(np.int64), _oracle_starts(batch))

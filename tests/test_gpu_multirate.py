@@ -70,6 +70,20 @@ def test_multirate_stages_match_oracle():
     _check_rooms(batch, plan, out, inter, range(len(batch["rt60"])))
 
 
+def test_multirate_edge_rooms():
+    """64 microphones, a near-field source, a 64-sample RIR (448 intermediate
+    samples: less than two filter chunks, one partial decimation tile),
+    48 kHz with 13 microphones, extreme reflection coefficients."""
+    import torch
+    from paper_2304_08052_amd import framrir as fr
+    batch = W.edge_cases()
+    plan = fr.Plan(batch, multirate=True)
+    say("multi-rate edge rooms")
+    out, table, inter = plan.forward_multirate()
+    torch.cuda.synchronize()
+    _check_rooms(batch, plan, out, inter, range(len(batch["rt60"])))
+
+
 def test_multirate_config2_sampled():
     import torch
     from paper_2304_08052_amd import autotune
