@@ -20,20 +20,26 @@ from . import framrir as fr
 
 N_CU = 256            # MI355X compute units
 LDS_PER_CU = 163840   # bytes
-STATIC_LDS = 2048     # the kernels' static LDS, bound from above
+
+
+def static_lds(threads):
+    """The render kernel's static LDS for a workgroup size, bounded from above
+    (per wave the bank-ordered pool, 128 pairs x 3 words, and 32 counts)."""
+    return 512 + (threads // 64) * (3 * 128 + 32) * 4
 
 
 def _per_cu_max(lds, threads, waves_per_simd):
     """Workgroups of one shape that fit a compute unit at once."""
-    return max(1, min(LDS_PER_CU // (lds + STATIC_LDS), waves_per_simd * 4 // (threads // 64)))
+    return max(1, min(LDS_PER_CU // (lds + static_lds(threads)), waves_per_simd * 4 // (threads // 64)))
 
 
 # (LDS tile, threads, waves per SIMD) x microphones per item x resident
 # workgroups per CU (the persistent grid is that many per CU)
 DEFAULT_CANDIDATES = [
     dict(lds_bytes=lds, wg_threads=t, waves_per_simd=w, max_mic_group=g, grid_wgs=N_CU * k)
-    for (lds, t, w) in [(131072, 1024, 4), (98304, 1024, 4), (114688, 1024, 4), (65536, 1024, 8),
-                        (65536, 512, 4), (49152, 512, 8), (40960, 512, 8), (32768, 256, 4)]
+    for (lds, t, w) in [(131072, 1024, 4), (98304, 1024, 4), (65536, 1024, 8), (49152, 1024, 8),
+                        (40960, 1024, 8), (65536, 512, 4), (49152, 512, 8), (40960, 512, 8), (32768, 256, 4)]
+    if lds + static_lds(t) <= LDS_PER_CU
     for g in (8, 4)
     for k in range(1, _per_cu_max(lds, t, w) + 1)
 ]

@@ -22,6 +22,12 @@ constexpr int kHalf = 40;          // taps are k - 40 .. k + 40 around k = floor
 constexpr int kHalo = 80;          // LDS guard samples on each side of a time tile
 constexpr int kMaxMicGroup = 16;   // microphones per work item
 constexpr int kBuckets = 1024;     // delay buckets of the per-source row order
+constexpr int kLdsBanks = 32;      // LDS banks of gfx950 (4 bytes each)
+constexpr int kPool = 128;         // render: pairs a wave ranks by bank per round (two per lane)
+// Static LDS of the render kernel for a workgroup of nt threads, bounded from
+// above: per wave the staged pool (3 words per pair) and the bank counts,
+// plus the microphone group and the item slot.
+constexpr int render_static_lds(int nt) { return 512 + (nt / 64) * (3 * kPool + kLdsBanks) * 4; }
 constexpr int kPartialStride = 3 * kMaxMicGroup + 4;   // backward partials per item
 
 enum TauCode : int32_t { kTauQuarter = 0, kTauHalf = 1, kTauOne = 2 };

@@ -212,56 +212,103 @@ __device__ __forceinline__ Pair pair_from_delay(double t, double D, double dx, d
 //   A P(m - dl) = S Q_m(dl),  Q_m(dl) = (-1)^(m+1) cos^2(pi (m - dl)/81) / (m - dl).
 // For |m| >= 3, Q_m is a short polynomial in dl (tap_poly.h); the taps next to
 // the centre keep the quotient, with cos(pi (m - dl)/81) from the angle-sum
-// identity; m = 0 is A sinc(dl) cos^2(pi dl/81), computed per pair.  Values
-// arrive pre-scaled to fixed point; +1/2 and floor round them to integers.
-// The tile accumulates them with ds_add_u32: gfx950 runs LDS integer atomics
-// ~20x faster than FP32 ones, and integer sums do not depend on the order of
-// the additions, so the output is bitwise reproducible.
-template <int J, int K>
-__device__ __forceinline__ float tap_horner(float dl) {
-    constexpr float c = kPolyCoef[J][K];
-    if constexpr (K == kPolyDeg[J]) {
-        return c;
+// identity; m = 0 is A sinc(dl) cos^2(pi dl/81), computed per pair.
+// Q_{-m}(dl) = -Q_m(-dl), and the table keeps that symmetry exactly, so taps
+// m and -m share one evaluation: with the even and odd parts
+// Q_m = E(dl^2) + dl O(dl^2),
+//   S Q_m = SE + SO,   S Q_{-m} = SO - SE,
+//   SE = sum_j c_{m,2j} w_j,   SO = sum_j c_{m,2j+1} v_j,
+// over per-pair powers w_j = S dl^2j, v_j = S dl^(2j+1): every coefficient is
+// an immediate operand of one multiply-add, summed from the highest term down.
+// Values arrive pre-scaled to fixed point; v_cvt_rpi_i32_f32 rounds them to
+// integers (floor(x + 1/2)).  The tile accumulates them with ds_add_u32:
+// gfx950 runs LDS integer atomics ~20x faster than FP32 ones, and integer sums
+// do not depend on the order of the additions, so the output is bitwise
+// reproducible.
+constexpr bool taps_mirrored() {
+    if (kPolyDeg[kHalf] >= 0) return false;
+    for (int m = 1; m <= kHalf; ++m) {
+        const int d = kPolyDeg[kHalf + m];
+        if (kPolyDeg[kHalf - m] != d) return false;
+        for (int k = 0; k <= d; ++k) {
+            const float c = kPolyCoef[kHalf + m][k];
+            if (kPolyCoef[kHalf - m][k] != ((k & 1) ? c : -c)) return false;
+        }
+    }
+    return true;
+}
+static_assert(taps_mirrored(), "the forward evaluates taps m and -m together");
+
+constexpr int poly_top() {
+    int d = 0;
+    for (int j = 0; j < kTaps; ++j) d = kPolyDeg[j] > d ? kPolyDeg[j] : d;
+    return d;
+}
+constexpr int kPolyTop = poly_top();
+constexpr int kPowTerms = kPolyTop / 2 + 1;   // w_j, v_j for j < kPowTerms
+
+// sum_{j = I}^{top} c_{J, 2j + P} pw_j, highest term first
+template <int J, int P, int I, int TOP>
+__device__ __forceinline__ float coef_chain(const float (&pw)[kPowTerms]) {
+    constexpr float c = kPolyCoef[J][2 * I + P];
+    if constexpr (I == TOP) {
+        return pw[I] * c;
     } else {
-        return __builtin_fmaf(tap_horner<J, K + 1>(dl), dl, c);
+        return __builtin_fmaf(pw[I], c, coef_chain<J, P, I + 1, TOP>(pw));
     }
 }
 
-// floor(v) as int32 in one VOP1 instruction (register operands only).
-__device__ __forceinline__ int cvt_floor_i32(float v) {
+// Nearest integer, floor(v + 1/2), in one VOP1 instruction (register operands only).
+__device__ __forceinline__ int cvt_rpi_i32(float v) {
     int q;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(q) : "v"(v));
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(q) : "v"(v));
     return q;
 }
 
-// Fixed-point tap value plus 1/2 (the caller floors it: round to nearest).
-template <int J>
-__device__ __forceinline__ float tap_value_half(float dl, float S, float cy, float sy, float v0h) {
-    constexpr int m = J - kHalf;
-    if constexpr (m == 0) {
-        return v0h;
-    } else if constexpr (kPolyDeg[J] < 0) {
-        constexpr float M = static_cast<float>(m);
-        constexpr float C = static_cast<float>(ct_cos(kPiOver81 * m));
-        constexpr float Sn = static_cast<float>(ct_sin(kPiOver81 * m));
-        constexpr float sgn = (m & 1) ? 1.0f : -1.0f;       // (-1)^(m+1)
-        const float rx = __builtin_amdgcn_rcpf(M - dl);
-        const float cw = __builtin_fmaf(C, cy, Sn * sy);
-        return __builtin_fmaf(S, (sgn * (cw * cw)) * rx, 0.5f);
+// Quotient form of a tap next to the centre (|m| = 1, 2).
+template <int m>
+__device__ __forceinline__ float tap_quotient(float dl, float S, float cy, float sy) {
+    constexpr float M = static_cast<float>(m);
+    constexpr float C = static_cast<float>(ct_cos(kPiOver81 * m));
+    constexpr float Sn = static_cast<float>(ct_sin(kPiOver81 * m));
+    constexpr float sgn = (m & 1) ? 1.0f : -1.0f;       // (-1)^(m+1)
+    const float rx = __builtin_amdgcn_rcpf(M - dl);
+    const float cw = __builtin_fmaf(C, cy, Sn * sy);
+    return S * ((sgn * (cw * cw)) * rx);
+}
+
+template <int M>
+__device__ __forceinline__ void fwd_pair(int* __restrict__ row, float dl, float S, float cy, float sy,
+                                         const float (&w)[kPowTerms], const float (&v)[kPowTerms]) {
+    constexpr int J = kHalf + M, D = kPolyDeg[J];
+    if constexpr (D < 0) {
+        atomicAdd(row + kHalf + M, cvt_rpi_i32(tap_quotient<M>(dl, S, cy, sy)));
+        atomicAdd(row + kHalf - M, cvt_rpi_i32(tap_quotient<-M>(dl, S, cy, sy)));
     } else {
-        return __builtin_fmaf(S, tap_horner<J, 0>(dl), 0.5f);
+        const float se = coef_chain<J, 0, 0, D / 2>(w);
+        float so = 0.0f;
+        if constexpr (D >= 1) so = coef_chain<J, 1, 0, (D - 1) / 2>(v);
+        atomicAdd(row + kHalf + M, cvt_rpi_i32(se + so));
+        atomicAdd(row + kHalf - M, cvt_rpi_i32(so - se));
     }
 }
 
-template <int J>
-__device__ __forceinline__ void fwd_tap(int* __restrict__ row, float dl, float S, float cy, float sy, float v0h) {
-    atomicAdd(row + J, cvt_floor_i32(tap_value_half<J>(dl, S, cy, sy, v0h)));
-}
-
-template <int... J>
-__device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, int* __restrict__ row, float dl, float S,
+// All 81 taps of one pair: the centre (v0 = S Q_0, pre-scaled) and the
+// mirrored pairs m = 1 .. 40.
+template <int... M>
+__device__ __forceinline__ void fwd_taps(std::integer_sequence<int, M...>, int* __restrict__ row, float dl, float S,
                                          float cy, float sy, float v0) {
-    (fwd_tap<J>(row, dl, S, cy, sy, v0), ...);
+    atomicAdd(row + kHalf, cvt_rpi_i32(v0));
+    const float z = dl * dl;
+    float w[kPowTerms], v[kPowTerms];
+    w[0] = S;
+    v[0] = S * dl;
+#pragma unroll
+    for (int j = 1; j < kPowTerms; ++j) {
+        w[j] = w[j - 1] * z;
+        v[j] = v[j - 1] * z;
+    }
+    (fwd_pair<M + 1>(row, dl, S, cy, sy, w, v), ...);
 }
 
 // ---- backward taps: s0 = sum_m G_m A P(m - dl), s1 = sum_m G_m A P'(m - dl)
@@ -275,13 +322,6 @@ __device__ __forceinline__ void fwd_taps(std::integer_sequence<int, J...>, int* 
 // The taps next to the centre use the closed form
 //   A P'(x) = (1/x) [(-1)^m (A cos(pi dl) w + (2 pi/81) S sw cw) - A P(x)],
 //   w = cw^2, cw = cos(pi x/81), sw = sin(pi x/81).
-constexpr int poly_top() {
-    int d = 0;
-    for (int j = 0; j < kTaps; ++j) d = kPolyDeg[j] > d ? kPolyDeg[j] : d;
-    return d;
-}
-constexpr int kPolyTop = poly_top();
-
 template <int J, int K>
 __device__ __forceinline__ void fold_coef(float G, float (&D)[kPolyTop + 1]) {
     if constexpr (K <= kPolyDeg[J]) D[K] = __builtin_fmaf(G, kPolyCoef[J][K], D[K]);
@@ -711,6 +751,107 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
 // ---------------------------------------------------------------------------
 // Render
 // ---------------------------------------------------------------------------
+// LDS bank-aware scheduling of the scatter.  gfx950's LDS has 32 banks of 4
+// bytes and serves an atomic instruction one half-wave (32 lanes) at a time;
+// a half-wave costs max(2, largest number of its lanes in one bank) cycles.
+// The lanes of one tap instruction address word (first tap + j) of their
+// pairs, so their banks are those of the first taps, shifted alike: pairs
+// whose first taps share a bank collide on all 81 taps.  A pool of 128 pairs
+// sorted by that bank and dealt round-robin to four half-waves puts at most
+// ceil(c / 4) pairs of a bank into one half-wave, c being the pool's pairs in
+// that bank (about Poisson(4)), against about Poisson(1) per bank for 32
+// lanes that take pairs as they come.  Integer sums do not depend on the
+// order, so neither does the output.
+
+// What a tap phase needs of a pair: the LDS word of its first tap, dl and
+// (A x fixed-point scale) sinc(dl); cos, sin of pi dl / 81 and S are
+// recomputed from dl.
+struct StagedPair {
+    int word;      // LDS word of tap 0, or -1 when the pair adds nothing to this tile
+    float dl;
+    float as;
+};
+
+template <typename Ctx>
+__device__ __forceinline__ StagedPair stage_pair(const Ctx& c, const double4& row, const double* q, int row_base,
+                                                 int shift, float scale, bool live) {
+    StagedPair sp{-1, 0.0f, 0.0f};
+    if (!live) return sp;
+    const Pair P = c.hr > 0.0 ? pair_setup_high_rate(row.x, row.y, row.z, q[0], q[1], q[2], c.c0, c.hr, c.lm1,
+                                                     c.rl, c.rh, render_row_amp(row.w))
+                              : pair_setup(row.x, row.y, row.z, q[0], q[1], q[2], c.fs_over_c, render_row_amp(row.w));
+    const int b0 = P.k + shift;   // tap 0 within the microphone's row
+    if (b0 < 0 || b0 + kTaps > c.rowlen) return sp;
+    sp.word = row_base + b0;
+    sp.dl = P.dl;
+    sp.as = (P.A * scale) * P.sinc;
+    return sp;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One round of a wave: rank the pool by bank, stage it in dealt order, run
+// the taps of two wave-steps (four half-waves).
+__device__ __forceinline__ void pool_round(int* __restrict__ acc, uint32_t* __restrict__ st, int* __restrict__ cnt,
+                                           int lane, const StagedPair& a, const StagedPair& b) {
+    if (lane < kLdsBanks) cnt[lane] = 0;
+    wave_sync();
+    const int ka = a.word & (kLdsBanks - 1), kb = b.word & (kLdsBanks - 1);
+    int ra = 0, rb = 0;
+    if (a.word >= 0) ra = atomicAdd(&cnt[ka], 1);
+    if (b.word >= 0) rb = atomicAdd(&cnt[kb], 1);
+    wave_sync();
+    // exclusive scan of the bank counts (lanes 0..31)
+    const int cv = lane < kLdsBanks ? cnt[lane] : 0;
+    int incl = cv;
+    for (int off = 1; off < kLdsBanks; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    const int n_pool = __shfl(incl, kLdsBanks - 1);
+    wave_sync();
+    if (lane < kLdsBanks) cnt[lane] = incl - cv;
+    wave_sync();
+    // position pi in bank order -> half-wave pi mod H, slot pi / H, with H
+    // = ceil(n_pool / 32) half-waves (a partly filled pool runs fewer)
+    const int H = (n_pool + 31) >> 5;
+    const int hmul = H == 3 ? 21846 : 65536 / max(H, 1);    // pi / H = (pi hmul) >> 16 for pi < 128
+    if (a.word >= 0) {
+        const int pi = cnt[ka] + ra, i = (pi * hmul) >> 16, q = (pi - i * H) * 32 + i;
+        st[q] = static_cast<uint32_t>(a.word);
+        st[kPool + q] = __float_as_uint(a.dl);
+        st[2 * kPool + q] = __float_as_uint(a.as);
+    }
+    if (b.word >= 0) {
+        const int pi = cnt[kb] + rb, i = (pi * hmul) >> 16, q = (pi - i * H) * 32 + i;
+        st[q] = static_cast<uint32_t>(b.word);
+        st[kPool + q] = __float_as_uint(b.dl);
+        st[2 * kPool + q] = __float_as_uint(b.as);
+    }
+    wave_sync();
+#pragma unroll 1
+    for (int step = 0; 2 * step < H; ++step) {
+        const int q = 64 * step + lane;                        // half-wave h = q / 32, slot i = q % 32
+        const int h = q >> 5;
+        if (h < H && (lane & 31) * H + h < n_pool) {
+            const int word = static_cast<int>(st[q]);
+            const float dl = __uint_as_float(st[kPool + q]);
+            const float as = __uint_as_float(st[2 * kPool + q]);
+            const float y = (kPiF / 81.0f) * dl;
+            const float y2 = y * y;
+            // |y| <= pi / 162: three Taylor terms are exact to FP32 rounding
+            const float cy = __builtin_fmaf(y2, __builtin_fmaf(y2, 1.0f / 24.0f, -0.5f), 1.0f);
+            const float sy = y * __builtin_fmaf(y2, __builtin_fmaf(y2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+            fwd_taps(std::make_integer_sequence<int, kHalf>{}, acc + word, dl, as * dl, cy, sy, as * (cy * cy));
+        }
+    }
+    wave_sync();
+}
+
 template <int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 render_kernel(const void* __restrict__ desc, const double* __restrict__ table, const double* __restrict__ mic,
@@ -720,6 +861,8 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
     extern __shared__ int acc[];
     __shared__ double micq[3 * kMaxMicGroup];
     __shared__ int s_item;
+    __shared__ uint32_t stage[NT / 64][3 * kPool];   // per wave: staged pairs of a round
+    __shared__ int bank_cnt[NT / 64][kLdsBanks];
     const DescHeader* H = hdr(desc);
     const int n_items = H->n_items;
     const int tid = threadIdx.x;
@@ -756,20 +899,20 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
         const int jstep = n_list > 0 ? static_cast<int>((static_cast<int64_t>(NT) * P) % n_list) : 0;
         __syncthreads();
         // ---- scatter the taps as rounded fixed-point integers.  Pair
-        // p = m * n_list + e: a wave takes rows of one microphone.
+        // p = m * n_list + e: a wave takes rows of one microphone.  Each
+        // round a wave sets up two pairs per lane (p and p + NT), ranks its
+        // pool of up to 128 by the LDS bank of the pair's first tap and
+        // deals that order round-robin into four half-waves, then runs the
+        // taps from the staged pairs (pool_round).
         const int n_pairs = n_list * mg;
-        int p = tid, m = 0, e = tid;        // (m, e) of p = tid + k NT, advanced without division
+        const int lane = tid & 63;
+        int m = 0, e = tid;                 // (m, e) of the lane's next pair, advanced without division
         while (e >= n_list && m < mg) {
             e -= n_list;
             ++m;
         }
         int j = n_list > 0 ? static_cast<int>((static_cast<int64_t>(e) * P) % n_list) : 0;
-        double4 row = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (p < n_pairs) row = rows[j];
-        while (p < n_pairs) {
-            const int cm = m;
-            const double4 cur = row;
-            p += NT;
+        auto advance = [&]() {
             e += NT;
             j += jstep;
             if (j >= n_list) j -= n_list;
@@ -777,18 +920,26 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
                 e -= n_list;
                 ++m;
             }
-            if (p < n_pairs) row = rows[j];   // prefetch the next pair's row
-            const Pair P = c.hr > 0.0
-                               ? pair_setup_high_rate(cur.x, cur.y, cur.z, micq[3 * cm], micq[3 * cm + 1],
-                                                      micq[3 * cm + 2], c.c0, c.hr, c.lm1, c.rl, c.rh,
-                                                      render_row_amp(cur.w))
-                               : pair_setup(cur.x, cur.y, cur.z, micq[3 * cm], micq[3 * cm + 1], micq[3 * cm + 2],
-                                            c.fs_over_c, render_row_amp(cur.w));
-            const int b0 = P.k + shift;
-            if (b0 < 0 || b0 + kTaps > c.rowlen) continue;
-            const float S = P.S * scale;
-            const float v0h = __builtin_fmaf((P.A * scale) * P.sinc, P.cy * P.cy, 0.5f);
-            fwd_taps(std::make_integer_sequence<int, kTaps>{}, acc + cm * c.rowlen + b0, P.dl, S, P.cy, P.sy, v0h);
+        };
+        double4 rowA = make_double4(0.0, 0.0, 0.0, 0.0), rowB = rowA;
+        int mA = m;
+        if (tid < n_pairs) rowA = rows[j];
+        advance();
+        int mB = m;
+        if (tid + NT < n_pairs) rowB = rows[j];
+        advance();
+        for (int p0 = tid - lane; p0 < n_pairs; p0 += 2 * NT) {   // wave-uniform: p0 is lane 0's pair
+            const int pA = p0 + lane, pB = pA + NT;
+            const StagedPair a = stage_pair(c, rowA, micq + 3 * mA, mA * c.rowlen, shift, scale, pA < n_pairs);
+            const StagedPair b = stage_pair(c, rowB, micq + 3 * mB, mB * c.rowlen, shift, scale, pB < n_pairs);
+            // the next round's rows load while this round's taps run
+            mA = m;
+            if (pA + 2 * NT < n_pairs) rowA = rows[j];
+            advance();
+            mB = m;
+            if (pB + 2 * NT < n_pairs) rowB = rows[j];
+            advance();
+            pool_round(acc, stage[tid >> 6], bank_cnt[tid >> 6], lane, a, b);
         }
         __syncthreads();
         // writeback of the tile core, samples [t0, min(t0 + len, T)), and
@@ -1418,7 +1569,7 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
     switch (key) {
 #define FR_CASE(NT, WPE)                                                                                    \
     case NT * 16 + WPE:                                                                                     \
-        if (int rc = allow_lds<render_kernel<NT, WPE>>()) return rc;                                          \
+        if (int rc = allow_lds<render_kernel<NT, WPE>, kLdsPerCu - render_static_lds(NT)>()) return rc;     \
         hipLaunchKernelGGL((render_kernel<NT, WPE>), grid, block, lds, st, desc_dev, table_dev, mic_dev,   \
                            src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off, w.sorted,         \
                            acc_words);                                                                      \

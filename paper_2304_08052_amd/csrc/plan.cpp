@@ -136,6 +136,9 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "waves_per_simd must be 4 or 8 (got %d)", launch.waves_per_simd);
     if (launch.wg_threads != 256 && launch.wg_threads != 512 && launch.wg_threads != 1024)
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "wg_threads must be 256, 512 or 1024 (got %d)", launch.wg_threads);
+    if (launch.lds_bytes + render_static_lds(launch.wg_threads) > kLdsPerCu)
+        return fr_fail(FRAMRIR_E_RANGE, "lds_bytes + the render's static LDS (%d) must not exceed %d (got %d)",
+                       render_static_lds(launch.wg_threads), kLdsPerCu, launch.lds_bytes);
     if (launch.lds_bytes < 28 * launch.wg_threads)
         return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be >= 28 * wg_threads (backward reduction)");
     if (launch.max_mic_group < 1 || launch.max_mic_group > kMaxMicGroup)
@@ -484,7 +487,7 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         multirate ? align(plan->ws_taps_off + static_cast<int64_t>(sizeof(float)) * kDecTapStride * n_rooms) : 0;
     int32_t grid = launch.grid_wgs;
     if (grid == 0) {
-        const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + kStaticLdsBytes);
+        const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + render_static_lds(launch.wg_threads));
         const int per_cu_waves = launch.waves_per_simd * 4 / (launch.wg_threads / 64);
         const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
         grid = static_cast<int32_t>(std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu));

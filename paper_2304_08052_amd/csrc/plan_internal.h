@@ -12,7 +12,6 @@
 // static scratch.
 constexpr int kLdsPerCu = 163840;
 constexpr int kMaxDynLdsBytes = 160000;
-constexpr int kStaticLdsBytes = 2048;
 
 // Compiled (threads per workgroup, waves per SIMD) shapes of the render and
 // backward kernels.
