@@ -78,6 +78,8 @@ def parse_args():
     p.add_argument("--max-mic-group", type=int, default=None)
     p.add_argument("--waves-per-simd", type=int, default=None)
     p.add_argument("--grid-wgs", type=int, default=None, help="workgroups of the persistent grid (0 = as many as fit)")
+    p.add_argument("--bwd-wg-threads", type=int, default=None, help="threads per backward workgroup (0 = as the render)")
+    p.add_argument("--bwd-grid-wgs", type=int, default=None, help="workgroups of the backward grid (0 = as many as fit)")
     p.add_argument("--tune", action="store_true", help="pick the launch shape with the autotuner first")
     p.add_argument("--per-room", action="store_true",
                    help="also time the plain per-room launch path on the same batch")
@@ -156,6 +158,10 @@ def main():
         launch["waves_per_simd"] = args.waves_per_simd
     if args.grid_wgs is not None:
         launch["grid_wgs"] = args.grid_wgs
+    if args.bwd_wg_threads is not None:
+        launch["bwd_wg_threads"] = args.bwd_wg_threads
+    if args.bwd_grid_wgs is not None:
+        launch["bwd_grid_wgs"] = args.bwd_grid_wgs
     if args.workload == "mixed":
         return run_mixed(args, batch, desc, launch)
     if args.workload == "multirate":

@@ -96,20 +96,29 @@ typedef struct framrir_params {
 
 /* Launch shape of the render and backward kernels (not part of the method):
  * lds_bytes      LDS accumulator budget per workgroup, a multiple of 16 in
- *                [4096, 143616] and >= 28 * wg_threads,
- * wg_threads     threads per workgroup: 256, 512 or 1024,
- * grid_wgs       workgroups of the persistent grid (0 = as many as fit on
- *                256 compute units at once, capped at the number of items),
+ *                [4096, 160000], >= 28 * the workgroup size of either kernel,
+ *                and at most 163840 - the render's static LDS, which is
+ *                512 + 1664 * wg_threads / 64 bytes (27136 for 1024 threads),
+ * wg_threads     threads per render workgroup: 256, 512 or 1024,
+ * grid_wgs       workgroups of the persistent render grid (0 = as many as fit
+ *                on 256 compute units at once, capped at the number of items),
  * max_mic_group  microphones per work item, 1 .. 16 (0 = 8),
- * waves_per_simd register budget: 4 or 8 resident waves per SIMD (0 = 4).
+ * waves_per_simd register budget: 4 or 8 resident waves per SIMD (0 = 4),
+ * bwd_wg_threads threads per backward workgroup: 0 (= wg_threads), 256, 512
+ *                or 1024,
+ * bwd_grid_wgs   workgroups of the persistent backward grid (0 = as many as
+ *                fit, capped at the number of items).
  * A time tile holds tile_len = floor(lds_bytes / 4 / m_group) - 160 samples
- * of m_group microphones; rooms whose RIR is longer are split in time. */
+ * of m_group microphones; rooms whose RIR is longer are split in time.  The
+ * backward runs over the same work items as the render. */
 typedef struct framrir_launch {
     int32_t lds_bytes;
     int32_t wg_threads;
     int32_t grid_wgs;
     int32_t max_mic_group;
     int32_t waves_per_simd;
+    int32_t bwd_wg_threads;
+    int32_t bwd_grid_wgs;
 } framrir_launch;
 
 /* Sizes of a plan. */

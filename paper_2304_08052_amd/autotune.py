@@ -102,7 +102,9 @@ def time_render(batch, launch, reps=5, warmup=2, params=None):
 
 
 def tune(batch, candidates=None, reps=5, params=None, store=True):
-    """Times every candidate on this batch; returns (best launch, results)."""
+    """Times every candidate render shape on this batch; returns (best launch,
+    results).  The backward workgroup size (bwd_wg_threads) is not tuned here:
+    shipped entries carry it where a different size measured faster."""
     results = []
     for cand in candidates or DEFAULT_CANDIDATES:
         launch = dict(fr.DEFAULT_LAUNCH, **cand)

@@ -1655,9 +1655,10 @@ extern "C" int framrir_render_backward_prepared(const framrir_plan* plan, const 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const RenderWs w = render_ws(plan, ws_dev);
     float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + plan->ws_part_off);
-    const int lds = std::max(plan->launch.lds_bytes, 32 * plan->launch.wg_threads);
-    const dim3 grid(plan->grid), block(plan->launch.wg_threads);
-    const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
+    const int nt = plan->launch.bwd_wg_threads;
+    const int lds = std::max(plan->launch.lds_bytes, 32 * nt);
+    const dim3 grid(plan->bwd_grid), block(nt);
+    const int key = nt * 16 + plan->launch.waves_per_simd;
     switch (key) {
 #define FR_CASE(NT, WPE)                                                                                      \
     case NT * 16 + WPE:                                                                                       \

@@ -102,9 +102,10 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     } else {
         prm = framrir_params{0.25, 1.0, -2.0, 2.0, 0.25, 1024, 4096, FRAMRIR_TAPS, 0u};
     }
-    framrir_launch launch = launch_in ? *launch_in : framrir_launch{131072, 1024, 0, 8, 4};
+    framrir_launch launch = launch_in ? *launch_in : framrir_launch{131072, 1024, 0, 8, 4, 0, 0};
     if (launch.max_mic_group == 0) launch.max_mic_group = 8;
     if (launch.waves_per_simd == 0) launch.waves_per_simd = 4;
+    if (launch.bwd_wg_threads == 0) launch.bwd_wg_threads = launch.wg_threads;
 
     // ---- method parameters
     if (!(std::isfinite(prm.alpha) && std::isfinite(prm.beta) && std::isfinite(prm.a) && std::isfinite(prm.b) &&
@@ -139,11 +140,15 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     if (launch.lds_bytes + render_static_lds(launch.wg_threads) > kLdsPerCu)
         return fr_fail(FRAMRIR_E_RANGE, "lds_bytes + the render's static LDS (%d) must not exceed %d (got %d)",
                        render_static_lds(launch.wg_threads), kLdsPerCu, launch.lds_bytes);
-    if (launch.lds_bytes < 28 * launch.wg_threads)
-        return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be >= 28 * wg_threads (backward reduction)");
+    if (launch.bwd_wg_threads != 256 && launch.bwd_wg_threads != 512 && launch.bwd_wg_threads != 1024)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "bwd_wg_threads must be 0, 256, 512 or 1024 (got %d)",
+                       launch.bwd_wg_threads);
+    if (launch.lds_bytes < 28 * std::max(launch.wg_threads, launch.bwd_wg_threads))
+        return fr_fail(FRAMRIR_E_RANGE, "lds_bytes must be >= 28 * the workgroup size (backward reduction)");
     if (launch.max_mic_group < 1 || launch.max_mic_group > kMaxMicGroup)
         return fr_fail(FRAMRIR_E_RANGE, "max_mic_group must be in [1, %d]", kMaxMicGroup);
-    if (launch.grid_wgs < 0) return fr_fail(FRAMRIR_E_RANGE, "grid_wgs must be >= 0");
+    if (launch.grid_wgs < 0 || launch.bwd_grid_wgs < 0)
+        return fr_fail(FRAMRIR_E_RANGE, "grid_wgs and bwd_grid_wgs must be >= 0");
 
     framrir_plan* plan = new (std::nothrow) framrir_plan();
     if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "out of host memory");
@@ -493,6 +498,14 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         grid = static_cast<int32_t>(std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu));
     }
     plan->grid = std::max(1, grid);
+    int32_t bwd_grid = launch.bwd_grid_wgs;
+    if (bwd_grid == 0 && launch.bwd_wg_threads == launch.wg_threads) bwd_grid = plan->grid;
+    if (bwd_grid == 0) {   // the backward's dynamic LDS is max(lds_bytes, 32 x threads); its static LDS is small
+        const int lds = std::max(launch.lds_bytes, 32 * launch.bwd_wg_threads) + 2048;
+        const int per_cu = std::max(1, std::min(kLdsPerCu / lds, launch.waves_per_simd * 4 / (launch.bwd_wg_threads / 64)));
+        bwd_grid = static_cast<int32_t>(std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu));
+    }
+    plan->bwd_grid = std::max(1, bwd_grid);
     *out = plan;
     return FRAMRIR_OK;
 }

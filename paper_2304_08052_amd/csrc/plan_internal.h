@@ -30,7 +30,8 @@ struct framrir_plan {
     std::vector<char> blob;
     int64_t ws_bytes = 0;
     int64_t ws_bwd_bytes = 0;
-    int32_t grid = 1;
+    int32_t grid = 1;       // render workgroups
+    int32_t bwd_grid = 1;   // backward workgroups
     // workspace layout: counters | per-source scale | bucket offsets | slot of
     // row 0 | per-room completion counts | delay-ordered rows (ws_bytes: the
     // render) | per-item partials (ws_bwd_bytes: the backward)

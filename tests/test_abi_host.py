@@ -133,6 +133,12 @@ def test_invalid_launch_rejected():
         fr.Plan(W.config1(), launch=dict(wg_threads=100), device="cpu")
     with pytest.raises(fr.FramrirError):
         fr.Plan(W.config1(), launch=dict(lds_bytes=1000000), device="cpu")
+    with pytest.raises(fr.FramrirError):
+        fr.Plan(W.config1(), launch=dict(bwd_wg_threads=384), device="cpu")
+    with pytest.raises(fr.FramrirError):   # the render's static LDS for 1024 threads leaves 136704 bytes
+        fr.Plan(W.config1(), launch=dict(lds_bytes=136720, wg_threads=1024), device="cpu")
+    fr.Plan(W.config1(), launch=dict(lds_bytes=136704, wg_threads=1024), device="cpu")
+    fr.Plan(W.config1(), launch=dict(lds_bytes=65536, wg_threads=512, bwd_wg_threads=1024), device="cpu")
 
 
 def test_work_items_cover_every_output_once():
