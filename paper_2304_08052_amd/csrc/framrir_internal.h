@@ -54,6 +54,7 @@ struct DescHeader {
     int64_t n_chunks;          // high-pass chunks of the batch
     int32_t max_out_tiles;     // decimation tiles per channel, at most
     int32_t max_rl;
+    int64_t src_order_bytes;   // byte offset of int32[n_src]: the sources by row count, largest first
 };
 
 struct RoomDesc {
@@ -126,6 +127,9 @@ FR_HD const WorkItem* items(const void* blob) {
 }
 FR_HD const int32_t* room_items(const void* blob) {
     return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(blob) + hdr(blob)->room_items_bytes);
+}
+FR_HD const int32_t* src_order(const void* blob) {
+    return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(blob) + hdr(blob)->src_order_bytes);
 }
 
 // ---------------------------------------------------------------------------

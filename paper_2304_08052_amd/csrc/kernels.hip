@@ -587,8 +587,8 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
     __shared__ int wsum[NW];
     __shared__ float s_rho;
     const DescHeader* H = hdr(desc);
-    const int s = blockIdx.x;
-    if (s >= H->n_src) return;
+    if (static_cast<int>(blockIdx.x) >= H->n_src) return;
+    const int s = src_order(desc)[blockIdx.x];
     const SrcDesc* S = srcs(desc) + s;
     const RoomDesc* R = rooms(desc) + S->room;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -627,13 +627,16 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
         }
     };
     if constexpr (DRAW) {
+        // two independent rows per lane and iteration: their FP64 chains overlap
 #pragma unroll 1
-        for (int c = w0; c < w1; c += 64) {
-            const int i = c + lane;
-            const bool valid = i < w1;
-            double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (valid) v = prep_row<true>(H, S, R, s, i, table, src, true);
-            count_run(i, valid, v);
+        for (int c = w0; c < w1; c += 128) {
+            const int i0 = c + lane, i1 = c + 64 + lane;
+            const bool valid0 = i0 < w1, valid1 = i1 < w1;
+            double4 v0 = make_double4(0.0, 0.0, 0.0, 0.0), v1 = v0;
+            if (valid0) v0 = prep_row<true>(H, S, R, s, i0, table, src, true);
+            if (valid1) v1 = prep_row<true>(H, S, R, s, i1, table, src, true);
+            count_run(i0, valid0, v0);
+            if (c + 64 < w1) count_run(i1, valid1, v1);
         }
     } else {
         for (int c = w0; c < w1; c += 4 * 64) {   // four loads in flight per lane

@@ -463,7 +463,13 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     H.src_bytes = align(H.room_bytes + static_cast<int64_t>(sizeof(RoomDesc)) * n_rooms);
     H.item_bytes = align(H.src_bytes + static_cast<int64_t>(sizeof(SrcDesc)) * src_row);
     H.room_items_bytes = align(H.item_bytes + static_cast<int64_t>(sizeof(WorkItem)) * it.size());
-    const int64_t total = align(H.room_items_bytes + static_cast<int64_t>(sizeof(int32_t)) * plan->room_items.size());
+    // the preparation takes the sources largest first, so that the workgroups
+    // that start last have the least to do
+    std::vector<int32_t> src_ord(src_row);
+    for (int32_t s = 0; s < src_row; ++s) src_ord[s] = s;
+    std::stable_sort(src_ord.begin(), src_ord.end(), [&](int32_t x, int32_t y) { return sd[x].n_img > sd[y].n_img; });
+    H.src_order_bytes = align(H.room_items_bytes + static_cast<int64_t>(sizeof(int32_t)) * plan->room_items.size());
+    const int64_t total = align(H.src_order_bytes + static_cast<int64_t>(sizeof(int32_t)) * src_ord.size());
     plan->blob.assign(static_cast<size_t>(total), 0);
     char* base = plan->blob.data();
     std::memcpy(base, &H, sizeof(H));
@@ -471,6 +477,7 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     std::memcpy(base + H.src_bytes, sd.data(), sizeof(SrcDesc) * sd.size());
     std::memcpy(base + H.item_bytes, it.data(), sizeof(WorkItem) * it.size());
     std::memcpy(base + H.room_items_bytes, plan->room_items.data(), sizeof(int32_t) * plan->room_items.size());
+    std::memcpy(base + H.src_order_bytes, src_ord.data(), sizeof(int32_t) * src_ord.size());
     plan->header = H;
 
     // ---- workspace
