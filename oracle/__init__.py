@@ -18,6 +18,9 @@ framrir  The method itself: room scalars (Eq. 2, 5), image draws (Sec. III-B,
 multirate  The paper-literal rendering: high-rate impulses (Eq. 7, 8),
          down-sampling, the 80 Hz high-pass and the second down-sampling
          (Sec. II).
+spatialize  Spatialisation and mixing of the training set-up (Sec. IV-A):
+         each dry signal convolved with its RIRs, the second speaker scaled
+         to the SIR and the noise to the SNR, the mixture as their sum.
 
 Every function is slow and direct on purpose: there is no blocking, fusion or
 reordering beyond what the paper's definitions state.

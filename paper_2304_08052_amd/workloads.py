@@ -207,6 +207,54 @@ def edge_cases():
     return _finish(d)
 
 
+def spatial_batch(n_rooms=256, seed=0):
+    """Rooms for the spatialisation workload (Sec. IV-A, the speed set-up of
+    Table 2): rooms U(3,10) x U(3,10) x U(2.5,4) m, T60 U(0.1,0.7) s, 16 kHz,
+    three sources per room (two speakers and a point-source noise) 0.3-6 m
+    from the array centre, the 4-microphone linear array of the evaluation
+    set (spacings 4, 8, 4 cm), seeds 10000 + b."""
+    rng = np.random.default_rng([1006, seed])
+    d = _empty()
+    for b in range(n_rooms):
+        size = np.array([rng.uniform(3.0, 10.0), rng.uniform(3.0, 10.0), rng.uniform(2.5, 4.0)])
+        rt60 = rng.uniform(0.1, 0.7)
+        centre = _inside(rng, size, WALL_MARGIN)
+        yaw = rng.uniform(0.0, 2.0 * np.pi)
+        off = np.array([-0.08, -0.04, 0.04, 0.08])
+        mics = np.stack([centre[0] + off * np.cos(yaw), centre[1] + off * np.sin(yaw), np.full(4, centre[2])], axis=1)
+        _add_room(d, rng, size, rt60, 16000.0, 10000 + b, 3, mics)
+    return _finish(d)
+
+
+def spatial_signals(batch, n_samples, seed=0):
+    """Seeded stand-ins for the dry signals of Sec. IV-A (the paper's speech and
+    noise corpora are not used).  Speakers: Gaussian noise under a random
+    syllable-rate envelope (2-6 Hz) with silent gaps, active on spans whose
+    overlap is at least half of their union; noise: white Gaussian over the
+    whole window.  SIR U(-6, 6) dB, SNR U(10, 20) dB.  Returns sig [B, 3, N]
+    (float32), sir_db [B], snr_db [B] (float32)."""
+    rng = np.random.default_rng([2006, seed])
+    B, N = len(batch["rt60"]), n_samples
+    sig = np.zeros((B, 3, N), dtype=np.float32)
+    t = np.arange(N) / 16000.0
+    for b in range(B):
+        l1, l2 = (int(rng.uniform(0.75, 1.0) * N) for _ in range(2))
+        spans = [(0, l1), (N - l2, N)]
+        if rng.uniform() < 0.5:
+            spans.reverse()
+        for s, (a, e) in enumerate(spans):
+            rate = rng.uniform(2.0, 6.0)
+            env = np.clip(np.sin(2.0 * np.pi * rate * t + rng.uniform(0, 2 * np.pi)), 0.0, None) ** 2
+            x = rng.standard_normal(N) * env * rng.uniform(0.2, 1.0)
+            x[:a] = 0.0
+            x[e:] = 0.0
+            sig[b, s] = x
+        sig[b, 2] = rng.standard_normal(N) * rng.uniform(0.05, 0.5)
+    sir = rng.uniform(-6.0, 6.0, B).astype(np.float32)
+    snr = rng.uniform(10.0, 20.0, B).astype(np.float32)
+    return sig, sir, snr
+
+
 def upstream_grad(shape_total, seed=0):
     """Seeded N(0, 1) FP32 upstream gradient for backward benchmarks."""
     rng = np.random.default_rng([3000, seed])
