@@ -299,6 +299,31 @@ int framrir_forward_multirate(const framrir_plan* plan, const void* desc_dev, do
 int framrir_multirate_filter(const framrir_plan* plan, const void* desc_dev, float* inter_dev, float* out_dev,
                              void* ws_dev, size_t ws_bytes, void* stream);
 
+/* ---- Spatialisation and mixing (Sec. IV-A: the on-the-fly training set-up).
+ * Every room of the plan has 3 sources: speakers 0 and 1 and the noise 2.
+ * Each dry signal is convolved with its rendered RIRs (the full linear
+ * convolution, kept for the utterance window of n_samples samples); speaker 1
+ * is scaled so that 10 log10(E0 / E1) = SIR and the noise so that
+ * 10 log10(E_sp / E2) = SNR, where E_s is the energy of source s's scaled
+ * images over all microphones and samples and E_sp that of the sum of the two
+ * speakers' images; the mixture is the sum of the three scaled images.
+ *
+ *   rir_dev     the plan's forward output, packed as framrir_render writes it
+ *               (for a multi-rate plan: the output at fs)
+ *   sig_dev     [n_src][n_samples] FP32 dry signals, sources in plan order
+ *   sir_db_dev, snr_db_dev   [n_rooms] FP32 (dB)
+ *   images_dev  out: [n_chan][n_samples] scaled images, channels in plan order
+ *               (per room [3][n_mic][n_samples])
+ *   mix_dev     out: [n_mic total][n_samples] mixtures, microphones in plan order
+ *   gains_dev   out: [n_src] the gains (1 for speaker 0; 0 for a silent source)
+ *   ws_dev      workspace of framrir_spatial_workspace bytes, 256-byte aligned
+ * RIRs longer than 16384 samples are not supported (FRAMRIR_E_UNSUPPORTED);
+ * enqueues only. */
+int framrir_spatial_workspace(const framrir_plan* plan, int32_t n_samples, size_t* ws_bytes);
+int framrir_spatialize(const framrir_plan* plan, const void* desc_dev, const float* rir_dev, const float* sig_dev,
+                       const float* sir_db_dev, const float* snr_db_dev, int32_t n_samples, float* images_dev,
+                       float* mix_dev, float* gains_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Initialises the counters at the start of a render / backward workspace
  * (enqueues one small kernel; no host synchronisation). */
 int framrir_workspace_init(void* ws_dev, size_t ws_bytes, void* stream);

@@ -1,0 +1,355 @@
+// gfx950 kernels of the spatialisation step of the on-the-fly training set-up
+// (Sec. IV-A): each dry signal is convolved with its rendered multi-channel
+// RIRs (overlap-save with a 32768-point real FFT held in one workgroup's LDS),
+// the images' energies give the gains of the sampled SIR and SNR, and the
+// scaled images are summed into the mixture.
+//
+//   fft_twiddle_kernel   exp(-2 pi i m / N) and exp(-2 pi i k / L), FP64 -> FP32
+//   spectrum_kernel      real spectrum of an RIR channel or of a signal block
+//   conv_block_kernel    product of the two spectra, inverse FFT, one output block
+//   spatial_gain_kernel  per room: image energies (FP64, fixed order) -> gains
+//   spatial_mix_kernel   scaled images (in place) and the mixture
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "../../include/framrir.h"
+#include "framrir_internal.h"
+#include "plan_internal.h"
+
+namespace framrir {
+namespace {
+
+constexpr int kFftN = 16384;             // complex points: a real FFT of kFftL samples, two per point
+constexpr int kFftL = 2 * kFftN;
+constexpr int kFftThreads = 1024;
+constexpr int kBins = kFftN + 1;         // bins of the real spectrum
+constexpr int kFftLds = kFftN * 8;       // bytes of one complex FP32 sequence
+constexpr int kSpatialSources = 3;       // two speakers and the noise (sources 0, 1, 2 of a room)
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
+
+__global__ void fft_twiddle_kernel(float2* __restrict__ tw, float2* __restrict__ rt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double s, c;
+    if (i < kFftN) {   // exp(-2 pi i m / N)
+        sincospi(-2.0 * i / kFftN, &s, &c);
+        tw[i] = make_float2(static_cast<float>(c), static_cast<float>(s));
+    }
+    if (i < kBins) {   // exp(-2 pi i k / L)
+        sincospi(-2.0 * i / kFftL, &s, &c);
+        rt[i] = make_float2(static_cast<float>(c), static_cast<float>(s));
+    }
+}
+
+// In-place forward DFT of kFftN points in LDS, natural order in and out:
+// radix-4 Stockham passes (stride Ns = 1, 4, ..., N/4).  Butterfly j takes
+// x[j + r N/4] (r = 0..3), multiplied by w^(r k N / (4 Ns)) with k = j mod Ns,
+// and writes its 4-point DFT to (j / Ns) 4 Ns + k + q Ns.  Every thread reads
+// its inputs, the workgroup synchronises, then writes.
+__device__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ tw) {
+    constexpr int Q = kFftN / 4 / kFftThreads;   // butterflies per thread and pass
+    const int tid = threadIdx.x;
+#pragma unroll 1
+    for (int shift = 0; shift < 14; shift += 2) {
+        const int Ns = 1 << shift;
+        float2 v[Q][4];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = tid + q * kFftThreads;
+            const int k = j & (Ns - 1);
+            const int step = k << (12 - shift);   // k N / (4 Ns)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[q][r] = a[j + r * (kFftN / 4)];
+            v[q][1] = cmul(v[q][1], tw[step]);
+            v[q][2] = cmul(v[q][2], tw[2 * step]);
+            v[q][3] = cmul(v[q][3], tw[3 * step]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = tid + q * kFftThreads;
+            const int k = j & (Ns - 1);
+            const int base = ((j >> shift) << (shift + 2)) + k;
+            const float2 s02 = cadd(v[q][0], v[q][2]), d02 = csub(v[q][0], v[q][2]);
+            const float2 s13 = cadd(v[q][1], v[q][3]), d13 = csub(v[q][1], v[q][3]);
+            const float2 jd13 = make_float2(d13.y, -d13.x);   // -i (v1 - v3)
+            a[base] = cadd(s02, s13);
+            a[base + Ns] = cadd(d02, jd13);
+            a[base + 2 * Ns] = csub(s02, s13);
+            a[base + 3 * Ns] = csub(d02, jd13);
+        }
+        __syncthreads();
+    }
+}
+
+// Room of a channel (binary search on the rooms' first channels).
+__device__ __forceinline__ int room_of_chan(const void* desc, int c) {
+    const DescHeader* H = hdr(desc);
+    const RoomDesc* R = rooms(desc);
+    int lo = 0, hi = H->n_rooms - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (R[mid].chan0 <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Spectrum of a real segment of kFftL samples: packed as z[n] = s[2n] + i
+// s[2n+1], transformed, then X[k] = (Z[k] + Z*[N-k]) / 2 - (i / 2) e^(-2 pi i k
+// / L) (Z[k] - Z*[N-k]) for k = 0..N.  Jobs: one per RIR channel (the RIR at
+// the start of the segment, zeros after it), then one per (source, block j)
+// (signal samples j B - (Tm - 1) + n, zeros outside [0, N_s)).
+__global__ void __launch_bounds__(kFftThreads) spectrum_kernel(const void* __restrict__ desc,
+                                                               const float* __restrict__ rir,
+                                                               const float* __restrict__ sig,
+                                                               const float2* __restrict__ tw,
+                                                               const float2* __restrict__ rt,
+                                                               float2* __restrict__ hspec,
+                                                               float2* __restrict__ xspec, int n_chan, int n_blk,
+                                                               int adv, int tm, int n_samples) {
+    extern __shared__ float2 a[];
+    const int job = blockIdx.x;
+    const float* seg;
+    int64_t first;          // sample index of segment position 0
+    int len;                // valid samples of the source sequence
+    float2* dst;
+    if (job < n_chan) {
+        const int b = room_of_chan(desc, job);
+        const RoomDesc& R = rooms(desc)[b];
+        seg = rir + R.out2_off + static_cast<int64_t>(job - R.chan0) * R.T_out;
+        first = 0;
+        len = R.T_out;
+        dst = hspec + static_cast<int64_t>(job) * kBins;
+    } else {
+        const int q = job - n_chan, s = q / n_blk, j = q % n_blk;
+        seg = sig + static_cast<int64_t>(s) * n_samples;
+        first = static_cast<int64_t>(j) * adv - (tm - 1);
+        len = n_samples;
+        dst = xspec + static_cast<int64_t>(q) * kBins;
+    }
+    for (int n = threadIdx.x; n < kFftN; n += kFftThreads) {
+        const int64_t i0 = first + 2 * n, i1 = i0 + 1;
+        a[n] = make_float2(i0 >= 0 && i0 < len ? seg[i0] : 0.0f, i1 >= 0 && i1 < len ? seg[i1] : 0.0f);
+    }
+    __syncthreads();
+    fft_lds(a, tw);
+    for (int k = threadIdx.x; k < kBins; k += kFftThreads) {
+        const float2 zk = a[k & (kFftN - 1)], zc = conj2(a[(kFftN - k) & (kFftN - 1)]);
+        const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+        const float2 d = cmul(rt[k], make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y)));
+        dst[k] = make_float2(e.x + d.y, e.y - d.x);   // e - i d
+    }
+}
+
+// One output block of one channel: P = X H, then the inverse real FFT by the
+// forward one: Z[k] = E[k] + i O[k], E = (P[k] + P*[N-k]) / 2, O = (P[k] -
+// P*[N-k]) e^(2 pi i k / L) / 2, z = conj(DFT(conj(Z))) / N, samples 2n and
+// 2n+1 = Re, Im z[n].  Samples Tm - 1 .. L - 1 of the block are the outputs
+// j B .. j B + B - 1 (overlap-save).
+__global__ void __launch_bounds__(kFftThreads) conv_block_kernel(const void* __restrict__ desc,
+                                                                 const float2* __restrict__ tw,
+                                                                 const float2* __restrict__ rt,
+                                                                 const float2* __restrict__ hspec,
+                                                                 const float2* __restrict__ xspec,
+                                                                 float* __restrict__ images, int n_blk, int adv,
+                                                                 int tm, int n_samples) {
+    extern __shared__ float2 a[];
+    const int c = blockIdx.x / n_blk, j = blockIdx.x % n_blk;
+    const int b = room_of_chan(desc, c);
+    const RoomDesc& R = rooms(desc)[b];
+    const int s = R.src0 + (c - R.chan0) / R.n_mic;
+    const float2* H = hspec + static_cast<int64_t>(c) * kBins;
+    const float2* X = xspec + (static_cast<int64_t>(s) * n_blk + j) * kBins;
+    for (int k = threadIdx.x; k < kFftN; k += kFftThreads) {
+        const float2 p = cmul(X[k], H[k]), pc = conj2(cmul(X[kFftN - k], H[kFftN - k]));
+        const float2 e = make_float2(0.5f * (p.x + pc.x), 0.5f * (p.y + pc.y));
+        const float2 o = cmul(conj2(rt[k]), make_float2(0.5f * (p.x - pc.x), 0.5f * (p.y - pc.y)));
+        a[k] = make_float2(e.x - o.y, -(e.y + o.x));   // conj(e + i o)
+    }
+    __syncthreads();
+    fft_lds(a, tw);
+    constexpr float inv_n = 1.0f / kFftN;
+    float* y = images + static_cast<int64_t>(c) * n_samples;
+    const int64_t o0 = static_cast<int64_t>(j) * adv - (tm - 1);   // output index of segment sample 0
+    for (int n = threadIdx.x; n < kFftN; n += kFftThreads) {
+        const float2 w = a[n];
+        const int64_t i0 = o0 + 2 * n, i1 = i0 + 1;
+        if (2 * n >= tm - 1 && i0 < n_samples) y[i0] = w.x * inv_n;
+        if (2 * n + 1 >= tm - 1 && i1 < n_samples) y[i1] = -w.y * inv_n;
+    }
+}
+
+// Per room: E1, E2, E12 = sum y0 y1 and En over all microphones and samples,
+// each thread summing a fixed set of samples, then a fixed reduction tree; the
+// gains (1, g2, gn) of the room's SIR and SNR (a silent source gets gain 0).
+__global__ void __launch_bounds__(kFftThreads) spatial_gain_kernel(const void* __restrict__ desc,
+                                                                   const float* __restrict__ images,
+                                                                   const float* __restrict__ sir_db,
+                                                                   const float* __restrict__ snr_db,
+                                                                   float* __restrict__ gains, int n_samples) {
+    __shared__ double red[4][kFftThreads];
+    const int b = blockIdx.x;
+    const RoomDesc& R = rooms(desc)[b];
+    const int tid = threadIdx.x;
+    const int64_t per = static_cast<int64_t>(R.n_mic) * n_samples;   // samples of one source's image
+    const float* y0 = images + static_cast<int64_t>(R.chan0) * n_samples;
+    const float* y1 = y0 + per;
+    const float* y2 = y1 + per;
+    double e1 = 0.0, e2 = 0.0, e12 = 0.0, en = 0.0;
+    for (int64_t i = tid; i < per; i += kFftThreads) {
+        const double a0 = y0[i], a1 = y1[i], a2 = y2[i];
+        e1 += a0 * a0;
+        e2 += a1 * a1;
+        e12 += a0 * a1;
+        en += a2 * a2;
+    }
+    red[0][tid] = e1;
+    red[1][tid] = e2;
+    red[2][tid] = e12;
+    red[3][tid] = en;
+    __syncthreads();
+    for (int w = kFftThreads / 2; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        e1 = red[0][0];
+        e2 = red[1][0];
+        e12 = red[2][0];
+        en = red[3][0];
+        const double g2 = e2 > 0.0 ? sqrt(e1 / (e2 * exp10(static_cast<double>(sir_db[b]) / 10.0))) : 0.0;
+        const double esp = e1 + 2.0 * g2 * e12 + g2 * g2 * e2;
+        const double gn = en > 0.0 ? sqrt(esp / (en * exp10(static_cast<double>(snr_db[b]) / 10.0))) : 0.0;
+        float* g = gains + R.src0;
+        g[0] = 1.0f;
+        g[1] = static_cast<float>(g2);
+        g[2] = static_cast<float>(gn);
+    }
+}
+
+// Scaled images (in place) and the mixture; blocks (chunk, room).
+__global__ void spatial_mix_kernel(const void* __restrict__ desc, float* __restrict__ images,
+                                   const float* __restrict__ gains, float* __restrict__ mix, int n_samples) {
+    const int b = blockIdx.y;
+    const RoomDesc& R = rooms(desc)[b];
+    const int64_t per = static_cast<int64_t>(R.n_mic) * n_samples;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= per) return;
+    float* y = images + static_cast<int64_t>(R.chan0) * n_samples;
+    const float* g = gains + R.src0;
+    const float v0 = y[i] * g[0], v1 = y[per + i] * g[1], v2 = y[2 * per + i] * g[2];
+    y[i] = v0;
+    y[per + i] = v1;
+    y[2 * per + i] = v2;
+    mix[static_cast<int64_t>(R.mic0) * n_samples + i] = (v0 + v1) + v2;
+}
+
+struct SpatialLayout {
+    int tm, adv, n_blk;
+    int64_t tw_off, rt_off, h_off, x_off, bytes;
+};
+
+int spatial_layout(const framrir_plan* plan, int32_t n_samples, SpatialLayout& L) {
+    if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "plan is NULL");
+    if (n_samples < 1) return fr_fail(FRAMRIR_E_INVALID_ARG, "n_samples = %d must be >= 1", n_samples);
+    int tm = 1;
+    for (const RoomDesc& R : plan->rooms) {
+        if (R.n_src != kSpatialSources)
+            return fr_fail(FRAMRIR_E_INVALID_ARG, "spatialisation needs 3 sources per room (two speakers, the noise)");
+        tm = std::max(tm, static_cast<int>(R.T_out));
+    }
+    if (tm > kFftN)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "RIRs of %d samples: the spatialisation takes at most %d", tm, kFftN);
+    auto align = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+    L.tm = tm;
+    L.adv = kFftL - tm + 1;
+    L.n_blk = static_cast<int>((static_cast<int64_t>(n_samples) + L.adv - 1) / L.adv);
+    L.tw_off = 0;
+    L.rt_off = align(L.tw_off + 8 * static_cast<int64_t>(kFftN));
+    L.h_off = align(L.rt_off + 8 * static_cast<int64_t>(kBins));
+    L.x_off = align(L.h_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_chan);
+    L.bytes = align(L.x_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_src * L.n_blk);
+    return FRAMRIR_OK;
+}
+
+int allow_fft_lds() {
+    static int status = [] {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(spectrum_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kFftLds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(conv_block_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kFftLds);
+        return e == hipSuccess ? 0 : static_cast<int>(e);
+    }();
+    if (status != 0)
+        return fr_fail(FRAMRIR_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(static_cast<hipError_t>(status)));
+    return FRAMRIR_OK;
+}
+
+int check(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fr_fail(FRAMRIR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return FRAMRIR_OK;
+}
+
+}  // namespace
+}  // namespace framrir
+
+using namespace framrir;
+
+extern "C" int framrir_spatial_workspace(const framrir_plan* plan, int32_t n_samples, size_t* ws_bytes) {
+    if (!ws_bytes) return fr_fail(FRAMRIR_E_INVALID_ARG, "ws_bytes is NULL");
+    SpatialLayout L;
+    if (int rc = spatial_layout(plan, n_samples, L)) return rc;
+    *ws_bytes = static_cast<size_t>(L.bytes);
+    return FRAMRIR_OK;
+}
+
+extern "C" int framrir_spatialize(const framrir_plan* plan, const void* desc_dev, const float* rir_dev,
+                                  const float* sig_dev, const float* sir_db_dev, const float* snr_db_dev,
+                                  int32_t n_samples, float* images_dev, float* mix_dev, float* gains_dev,
+                                  void* ws_dev, size_t ws_bytes, void* stream) {
+    SpatialLayout L;
+    if (int rc = spatial_layout(plan, n_samples, L)) return rc;
+    if (!desc_dev || !rir_dev || !sig_dev || !sir_db_dev || !snr_db_dev || !images_dev || !mix_dev || !gains_dev ||
+        !ws_dev)
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws_dev) % 256 != 0 || reinterpret_cast<uintptr_t>(desc_dev) % 256 != 0)
+        return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned buffer");
+    if (static_cast<int64_t>(ws_bytes) < L.bytes)
+        return fr_fail(FRAMRIR_E_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, static_cast<long long>(L.bytes));
+    if (int rc = allow_fft_lds()) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws_dev);
+    float2* tw = reinterpret_cast<float2*>(w + L.tw_off);
+    float2* rt = reinterpret_cast<float2*>(w + L.rt_off);
+    float2* hspec = reinterpret_cast<float2*>(w + L.h_off);
+    float2* xspec = reinterpret_cast<float2*>(w + L.x_off);
+    const int n_chan = plan->header.n_chan, n_src = plan->header.n_src, n_rooms = plan->header.n_rooms;
+    hipLaunchKernelGGL(fft_twiddle_kernel, dim3((kBins + 255) / 256), dim3(256), 0, st, tw, rt);
+    if (int rc = check("fft_twiddle_kernel")) return rc;
+    hipLaunchKernelGGL(spectrum_kernel, dim3(n_chan + n_src * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev,
+                       rir_dev, sig_dev, tw, rt, hspec, xspec, n_chan, L.n_blk, L.adv, L.tm, n_samples);
+    if (int rc = check("spectrum_kernel")) return rc;
+    hipLaunchKernelGGL(conv_block_kernel, dim3(n_chan * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev, tw, rt,
+                       hspec, xspec, images_dev, L.n_blk, L.adv, L.tm, n_samples);
+    if (int rc = check("conv_block_kernel")) return rc;
+    hipLaunchKernelGGL(spatial_gain_kernel, dim3(n_rooms), dim3(kFftThreads), 0, st, desc_dev, images_dev, sir_db_dev,
+                       snr_db_dev, gains_dev, n_samples);
+    if (int rc = check("spatial_gain_kernel")) return rc;
+    int max_per = 0;
+    for (const RoomDesc& R : plan->rooms) max_per = std::max(max_per, R.n_mic);
+    const int64_t per = static_cast<int64_t>(max_per) * n_samples;
+    hipLaunchKernelGGL(spatial_mix_kernel, dim3(static_cast<unsigned>((per + 255) / 256), n_rooms), dim3(256), 0, st,
+                       desc_dev, images_dev, gains_dev, mix_dev, n_samples);
+    return check("spatial_mix_kernel");
+}

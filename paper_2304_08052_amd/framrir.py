@@ -75,6 +75,9 @@ EXPORTS = {
     "framrir_early": (ctypes.c_int, [ctypes.c_void_p] * 8),
     "framrir_forward_multirate": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_multirate_filter": (ctypes.c_int, [ctypes.c_void_p] * 5 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_spatial_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "framrir_spatialize": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int32] + [ctypes.c_void_p] * 4
+                           + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_philox4x32": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_void_p]),
     "framrir_host_cbrt_rn": (ctypes.c_int, [ctypes.c_void_p] * 2 + [ctypes.c_int64]),
@@ -324,6 +327,31 @@ class Plan:
         _check(lib().framrir_multirate_filter(self._h, _ptr(desc), _ptr(inter), _ptr(out), _ptr(ws), ws.numel(),
                                               _stream(stream)))
         return out
+
+    def spatial_workspace_bytes(self, n_samples):
+        n = ctypes.c_size_t(0)
+        _check(lib().framrir_spatial_workspace(self._h, int(n_samples), ctypes.byref(n)))
+        return int(n.value)
+
+    def spatialize(self, rir, sig, sir_db, snr_db, images=None, mix=None, gains=None, ws=None, stream=None,
+                   desc=None):
+        """framrir_spatialize: rooms of 3 sources (speakers 0, 1, noise 2); sig
+        [n_src, N] FP32 dry signals, sir_db / snr_db [n_rooms] FP32; returns
+        (images [n_chan, N], mix [n_mic, N], gains [n_src])."""
+        import torch
+        n = int(sig.shape[-1])
+        assert sig.dtype == torch.float32 and sig.is_contiguous() and sig.numel() == self.info.n_src * n
+        images = torch.empty((self.info.n_chan, n), dtype=torch.float32, device=self.device) if images is None \
+            else images
+        mix = torch.empty((self.info.n_mic, n), dtype=torch.float32, device=self.device) if mix is None else mix
+        gains = torch.empty(self.info.n_src, dtype=torch.float32, device=self.device) if gains is None else gains
+        if ws is None:
+            ws = torch.empty(self.spatial_workspace_bytes(n), dtype=torch.uint8, device=self.device)
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_spatialize(self._h, _ptr(desc), _ptr(rir), _ptr(sig), _ptr(sir_db), _ptr(snr_db), n,
+                                        _ptr(images), _ptr(mix), _ptr(gains), _ptr(ws), ws.numel(),
+                                        _stream(stream)))
+        return images, mix, gains
 
     def early(self, out, early=None, start=None, mic=None, src=None, stream=None, desc=None):
         """framrir_early: the Eq. 9 windows of rendered RIRs `out`; returns

@@ -207,7 +207,7 @@ def edge_cases():
     return _finish(d)
 
 
-def spatial_batch(n_rooms=256, seed=0):
+def spatial_batch(n_rooms=256, seed=0, rt60_range=(0.1, 0.7)):
     """Rooms for the spatialisation workload (Sec. IV-A, the speed set-up of
     Table 2): rooms U(3,10) x U(3,10) x U(2.5,4) m, T60 U(0.1,0.7) s, 16 kHz,
     three sources per room (two speakers and a point-source noise) 0.3-6 m
@@ -217,7 +217,7 @@ def spatial_batch(n_rooms=256, seed=0):
     d = _empty()
     for b in range(n_rooms):
         size = np.array([rng.uniform(3.0, 10.0), rng.uniform(3.0, 10.0), rng.uniform(2.5, 4.0)])
-        rt60 = rng.uniform(0.1, 0.7)
+        rt60 = rng.uniform(*rt60_range)
         centre = _inside(rng, size, WALL_MARGIN)
         yaw = rng.uniform(0.0, 2.0 * np.pi)
         off = np.array([-0.08, -0.04, 0.04, 0.08])
