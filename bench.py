@@ -68,7 +68,8 @@ def parse_args():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="batched", choices=["batched", "long", "mixed", "one", "multirate"])
+    p.add_argument("--workload", default="batched", choices=["batched", "long", "mixed", "one", "multirate",
+                                                              "spatial"])
     p.add_argument("--cpu-rooms", type=int, default=192,
                    help="rooms of the workload timed through the FP64 oracle on one host core (0 = skip)")
     p.add_argument("--no-graph", action="store_true")
@@ -146,7 +147,6 @@ def main():
     from paper_2304_08052_amd import framrir as fr
     from paper_2304_08052_amd import workloads as W
 
-    batch, desc = workload(args.workload)
     launch = {}
     if args.lds_bytes:
         launch["lds_bytes"] = args.lds_bytes
@@ -162,6 +162,9 @@ def main():
         launch["bwd_wg_threads"] = args.bwd_wg_threads
     if args.bwd_grid_wgs is not None:
         launch["bwd_grid_wgs"] = args.bwd_grid_wgs
+    if args.workload == "spatial":
+        return run_spatial(args, launch)
+    batch, desc = workload(args.workload)
     if args.workload == "mixed":
         return run_mixed(args, batch, desc, launch)
     if args.workload == "multirate":
@@ -359,6 +362,130 @@ def main():
         "autotune_top": tuned,
     }
     print(json.dumps(line), flush=True)
+
+
+def spatial_hbm_bytes(plan, n):
+    """Algorithmic HBM bytes of one framrir_spatialize call: the RIR spectra
+    (written once, read by each of the channel's blocks), the signal-block
+    spectra (written once, read by each microphone's channel), the RIRs and
+    signals read, the images written, read for the energies, then read and
+    written scaled, and the mixtures written."""
+    import numpy as np
+    bins = 16385 * 8
+    tm = int(np.max(plan.T))
+    n_blk = -(-n // (32768 - tm + 1))
+    n_chan, n_src, n_mic = plan.info.n_chan, plan.info.n_src, plan.info.n_mic
+    spectra = n_chan * bins * (1 + n_blk) + n_src * n_blk * bins * (1 + 4)
+    inputs = 4 * int(plan.info.out_floats) + 4 * n_src * n_blk * 32768
+    images = 4 * 4 * n_chan * n
+    return spectra + inputs + images + 4 * n_mic * n
+
+
+def run_spatial(args, launch):
+    """On-the-fly generation of training mixtures (Sec. IV-A, the speed
+    experiment of Table 2): per step the RIRs of 256 rooms (3 sources, 4-mic
+    array) are synthesised, then the two speakers and the noise are convolved
+    with them and mixed at the sampled SIR and SNR (4 s windows at 16 kHz)."""
+    import numpy as np
+    import torch
+    from paper_2304_08052_amd import autotune
+    from paper_2304_08052_amd import framrir as fr
+    from paper_2304_08052_amd import workloads as W
+    batch = W.spatial_batch(256)
+    n = 64000
+    if not launch:
+        launch = autotune.launch_for(batch)
+    plan = fr.Plan(batch, launch=launch)
+    sig, sir, snr = W.spatial_signals(batch, n)
+    sig_d = torch.from_numpy(sig.reshape(-1, n)).cuda()
+    sir_d, snr_d = torch.from_numpy(sir).cuda(), torch.from_numpy(snr).cuda()
+    table, out, ws = plan.empty_table(), plan.empty_out(), plan.workspace()
+    images = torch.empty((plan.info.n_chan, n), dtype=torch.float32, device="cuda")
+    mix = torch.empty((plan.info.n_mic, n), dtype=torch.float32, device="cuda")
+    gains = torch.empty(plan.info.n_src, dtype=torch.float32, device="cuda")
+    ws_sp = torch.empty(plan.spatial_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def spatial():
+        plan.spatialize(out, sig_d, sir_d, snr_d, images=images, mix=mix, gains=gains, ws=ws_sp)
+
+    def step():
+        plan.forward(table=table, out=out, ws=ws)
+        spatial()
+
+    def timed(fn, k):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    eager_ms = timed(step, args.steps)
+    graph_ms = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = timed(g.replay, args.steps)
+    spatial_ms = timed(spatial, args.steps)
+    step_ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
+    hbm = spatial_hbm_bytes(plan, n)
+    achieved = hbm / (spatial_ms * 1e-3) / 1e9
+    line = {
+        "metric": "training mixtures/sec generated on the fly (RIRs + spatialisation + SIR/SNR mixing), batch 256",
+        "value": 256 / (step_ms * 1e-3), "unit": "mixtures/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256 rooms U(3,10)xU(3,10)xU(2.5,4) m, T60 U(0.1,0.7) s, 16 kHz, 2 speakers + "
+                               "1 noise source, 4-mic linear array (4-8-4 cm), 4 s windows, SIR U(-6,6) dB, "
+                               "SNR U(10,20) dB",
+                   "rooms": 256, "samples": n, "launch": plan.launch},
+        "roofline": {"bound": "hbm", "kernel": "framrir_spatialize (spectra, products + inverse FFTs, energies, "
+                                              "mixing)", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": hbm,
+                     "spatial_ms": spatial_ms},
+        "eager_ms_per_step": eager_ms, "graph_ms_per_step": graph_ms,
+        "cpu_baseline": None,
+    }
+    if args.cpu_rooms > 0:
+        line["cpu_baseline"] = cpu_baseline_spatial(batch, sig, sir, snr, n, min(4, args.cpu_rooms))
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_spatial(batch, sig, sir, snr, n, n_rooms):
+    """The FP64 oracles (RIRs, then spatialisation) on the first n_rooms rooms, one thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:      # pragma: no cover
+        threadpool_limits = None
+    from oracle import framrir as F
+    from oracle import spatialize as SP
+    rooms = F.rooms_from_batch(batch)[:n_rooms]
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    t0 = time.perf_counter()
+    for b, rm in enumerate(rooms):
+        h = F.render_room(F.room_plan(rm, F.Params()), rm)
+        SP.spatialize_room(h, sig[b].astype(float), float(sir[b]), float(snr[b]), n)
+    dt = time.perf_counter() - t0
+    if ctx is not None:
+        ctx.unregister() if hasattr(ctx, "unregister") else None
+    return dict(value=n_rooms / dt, unit="mixtures/s", cores=1, kind="oracle",
+                sample=f"first {n_rooms} rooms of the same workload (RIRs and spatialisation), FP64 numpy oracle, "
+                       f"{dt:.2f} s on 1 thread")
 
 
 def run_multirate(args, batch, desc, launch):

@@ -7,7 +7,8 @@
 //   fft_twiddle_kernel   exp(-2 pi i m / N) and exp(-2 pi i k / L), FP64 -> FP32
 //   spectrum_kernel      real spectrum of an RIR channel or of a signal block
 //   conv_block_kernel    product of the two spectra, inverse FFT, one output block
-//   spatial_gain_kernel  per room: image energies (FP64, fixed order) -> gains
+//   spatial_energy_kernel  per room: image energies (FP64, fixed order), in parts
+//   spatial_gain_kernel  per room: the parts summed in order -> gains of the SIR and SNR
 //   spatial_mix_kernel   scaled images (in place) and the mixture
 #include <hip/hip_runtime.h>
 
@@ -25,7 +26,13 @@ constexpr int kFftN = 16384;             // complex points: a real FFT of kFftL 
 constexpr int kFftL = 2 * kFftN;
 constexpr int kFftThreads = 1024;
 constexpr int kBins = kFftN + 1;         // bins of the real spectrum
-constexpr int kFftLds = kFftN * 8;       // bytes of one complex FP32 sequence
+// LDS: the sequence at padded positions i + i / 16 (the Stockham passes'
+// strided writes then rarely meet in a bank), then two twiddle tables:
+// w^m = T1[m / 64] T2[m mod 64], T1[h] = w^(64 h), T2[l] = w^l.
+constexpr int kPadded = kFftN + kFftN / 16;
+constexpr int kT1 = kFftN / 64, kT2 = 64;
+constexpr int kFftLds = (kPadded + kT1 + kT2) * 8;
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 constexpr int kSpatialSources = 3;       // two speakers and the noise (sources 0, 1, 2 of a room)
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -52,8 +59,9 @@ __global__ void fft_twiddle_kernel(float2* __restrict__ tw, float2* __restrict__
 // radix-4 Stockham passes (stride Ns = 1, 4, ..., N/4).  Butterfly j takes
 // x[j + r N/4] (r = 0..3), multiplied by w^(r k N / (4 Ns)) with k = j mod Ns,
 // and writes its 4-point DFT to (j / Ns) 4 Ns + k + q Ns.  Every thread reads
-// its inputs, the workgroup synchronises, then writes.
-__device__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ tw) {
+// its inputs, the workgroup synchronises, then writes.  a is addressed
+// through pidx; t1, t2 are the twiddle tables in LDS.
+__device__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ t1, const float2* __restrict__ t2) {
     constexpr int Q = kFftN / 4 / kFftThreads;   // butterflies per thread and pass
     const int tid = threadIdx.x;
 #pragma unroll 1
@@ -66,10 +74,12 @@ __device__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ tw) {
             const int k = j & (Ns - 1);
             const int step = k << (12 - shift);   // k N / (4 Ns)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[q][r] = a[j + r * (kFftN / 4)];
-            v[q][1] = cmul(v[q][1], tw[step]);
-            v[q][2] = cmul(v[q][2], tw[2 * step]);
-            v[q][3] = cmul(v[q][3], tw[3 * step]);
+            for (int r = 0; r < 4; ++r) v[q][r] = a[pidx(j + r * (kFftN / 4))];
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                const int m = r * step;
+                v[q][r] = cmul(v[q][r], cmul(t1[m >> 6], t2[m & 63]));
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -80,13 +90,19 @@ __device__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ tw) {
             const float2 s02 = cadd(v[q][0], v[q][2]), d02 = csub(v[q][0], v[q][2]);
             const float2 s13 = cadd(v[q][1], v[q][3]), d13 = csub(v[q][1], v[q][3]);
             const float2 jd13 = make_float2(d13.y, -d13.x);   // -i (v1 - v3)
-            a[base] = cadd(s02, s13);
-            a[base + Ns] = cadd(d02, jd13);
-            a[base + 2 * Ns] = csub(s02, s13);
-            a[base + 3 * Ns] = csub(d02, jd13);
+            a[pidx(base)] = cadd(s02, s13);
+            a[pidx(base + Ns)] = cadd(d02, jd13);
+            a[pidx(base + 2 * Ns)] = csub(s02, s13);
+            a[pidx(base + 3 * Ns)] = csub(d02, jd13);
         }
         __syncthreads();
     }
+}
+
+// The twiddle tables into LDS (after the sequence).
+__device__ __forceinline__ void load_twiddles(float2* a, const float2* __restrict__ tw) {
+    float2* t1 = a + kPadded;
+    for (int i = threadIdx.x; i < kT1 + kT2; i += kFftThreads) t1[i] = i < kT1 ? tw[64 * i] : tw[i - kT1];
 }
 
 // Room of a channel (binary search on the rooms' first channels).
@@ -135,14 +151,22 @@ __global__ void __launch_bounds__(kFftThreads) spectrum_kernel(const void* __res
         len = n_samples;
         dst = xspec + static_cast<int64_t>(q) * kBins;
     }
-    for (int n = threadIdx.x; n < kFftN; n += kFftThreads) {
-        const int64_t i0 = first + 2 * n, i1 = i0 + 1;
-        a[n] = make_float2(i0 >= 0 && i0 < len ? seg[i0] : 0.0f, i1 >= 0 && i1 < len ? seg[i1] : 0.0f);
+    constexpr int G = 4;   // iterations whose loads are in flight together
+    for (int n0 = threadIdx.x; n0 < kFftN; n0 += G * kFftThreads) {
+        float2 v[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t i0 = first + 2 * (n0 + g * kFftThreads), i1 = i0 + 1;
+            v[g] = make_float2(i0 >= 0 && i0 < len ? seg[i0] : 0.0f, i1 >= 0 && i1 < len ? seg[i1] : 0.0f);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) a[pidx(n0 + g * kFftThreads)] = v[g];
     }
+    load_twiddles(a, tw);
     __syncthreads();
-    fft_lds(a, tw);
+    fft_lds(a, a + kPadded, a + kPadded + kT1);
     for (int k = threadIdx.x; k < kBins; k += kFftThreads) {
-        const float2 zk = a[k & (kFftN - 1)], zc = conj2(a[(kFftN - k) & (kFftN - 1)]);
+        const float2 zk = a[pidx(k & (kFftN - 1))], zc = conj2(a[pidx((kFftN - k) & (kFftN - 1))]);
         const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 d = cmul(rt[k], make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y)));
         dst[k] = make_float2(e.x + d.y, e.y - d.x);   // e - i d
@@ -168,19 +192,34 @@ __global__ void __launch_bounds__(kFftThreads) conv_block_kernel(const void* __r
     const int s = R.src0 + (c - R.chan0) / R.n_mic;
     const float2* H = hspec + static_cast<int64_t>(c) * kBins;
     const float2* X = xspec + (static_cast<int64_t>(s) * n_blk + j) * kBins;
-    for (int k = threadIdx.x; k < kFftN; k += kFftThreads) {
-        const float2 p = cmul(X[k], H[k]), pc = conj2(cmul(X[kFftN - k], H[kFftN - k]));
-        const float2 e = make_float2(0.5f * (p.x + pc.x), 0.5f * (p.y + pc.y));
-        const float2 o = cmul(conj2(rt[k]), make_float2(0.5f * (p.x - pc.x), 0.5f * (p.y - pc.y)));
-        a[k] = make_float2(e.x - o.y, -(e.y + o.x));   // conj(e + i o)
+    constexpr int G = 4;   // iterations whose loads are in flight together
+    for (int k0 = threadIdx.x; k0 < kFftN; k0 += G * kFftThreads) {
+        float2 xa[G], ha[G], xb[G], hb[G], w[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int k = k0 + g * kFftThreads;
+            xa[g] = X[k];
+            ha[g] = H[k];
+            xb[g] = X[kFftN - k];
+            hb[g] = H[kFftN - k];
+            w[g] = rt[k];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const float2 p = cmul(xa[g], ha[g]), pc = conj2(cmul(xb[g], hb[g]));
+            const float2 e = make_float2(0.5f * (p.x + pc.x), 0.5f * (p.y + pc.y));
+            const float2 o = cmul(conj2(w[g]), make_float2(0.5f * (p.x - pc.x), 0.5f * (p.y - pc.y)));
+            a[pidx(k0 + g * kFftThreads)] = make_float2(e.x - o.y, -(e.y + o.x));   // conj(e + i o)
+        }
     }
+    load_twiddles(a, tw);
     __syncthreads();
-    fft_lds(a, tw);
+    fft_lds(a, a + kPadded, a + kPadded + kT1);
     constexpr float inv_n = 1.0f / kFftN;
     float* y = images + static_cast<int64_t>(c) * n_samples;
     const int64_t o0 = static_cast<int64_t>(j) * adv - (tm - 1);   // output index of segment sample 0
     for (int n = threadIdx.x; n < kFftN; n += kFftThreads) {
-        const float2 w = a[n];
+        const float2 w = a[pidx(n)];
         const int64_t i0 = o0 + 2 * n, i1 = i0 + 1;
         if (2 * n >= tm - 1 && i0 < n_samples) y[i0] = w.x * inv_n;
         if (2 * n + 1 >= tm - 1 && i1 < n_samples) y[i1] = -w.y * inv_n;
@@ -188,15 +227,17 @@ __global__ void __launch_bounds__(kFftThreads) conv_block_kernel(const void* __r
 }
 
 // Per room: E1, E2, E12 = sum y0 y1 and En over all microphones and samples,
-// each thread summing a fixed set of samples, then a fixed reduction tree; the
-// gains (1, g2, gn) of the room's SIR and SNR (a silent source gets gain 0).
-__global__ void __launch_bounds__(kFftThreads) spatial_gain_kernel(const void* __restrict__ desc,
-                                                                   const float* __restrict__ images,
-                                                                   const float* __restrict__ sir_db,
-                                                                   const float* __restrict__ snr_db,
-                                                                   float* __restrict__ gains, int n_samples) {
-    __shared__ double red[4][kFftThreads];
-    const int b = blockIdx.x;
+// split over kEnergyParts workgroups (blocks (part, room)), each thread
+// summing a fixed set of samples in FP64, then a fixed reduction tree; one
+// set of partial sums per workgroup.
+constexpr int kEnergyParts = 16;
+constexpr int kEnergyThreads = 256;
+__global__ void __launch_bounds__(kEnergyThreads) spatial_energy_kernel(const void* __restrict__ desc,
+                                                                        const float* __restrict__ images,
+                                                                        double* __restrict__ partials,
+                                                                        int n_samples) {
+    __shared__ double red[4][kEnergyThreads];
+    const int part = blockIdx.x, b = blockIdx.y;
     const RoomDesc& R = rooms(desc)[b];
     const int tid = threadIdx.x;
     const int64_t per = static_cast<int64_t>(R.n_mic) * n_samples;   // samples of one source's image
@@ -204,7 +245,8 @@ __global__ void __launch_bounds__(kFftThreads) spatial_gain_kernel(const void* _
     const float* y1 = y0 + per;
     const float* y2 = y1 + per;
     double e1 = 0.0, e2 = 0.0, e12 = 0.0, en = 0.0;
-    for (int64_t i = tid; i < per; i += kFftThreads) {
+    for (int64_t i = static_cast<int64_t>(part) * kEnergyThreads + tid; i < per;
+         i += static_cast<int64_t>(kEnergyParts) * kEnergyThreads) {
         const double a0 = y0[i], a1 = y1[i], a2 = y2[i];
         e1 += a0 * a0;
         e2 += a1 * a1;
@@ -216,24 +258,33 @@ __global__ void __launch_bounds__(kFftThreads) spatial_gain_kernel(const void* _
     red[2][tid] = e12;
     red[3][tid] = en;
     __syncthreads();
-    for (int w = kFftThreads / 2; w > 0; w >>= 1) {
+    for (int w = kEnergyThreads / 2; w > 0; w >>= 1) {
         if (tid < w)
             for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + w];
         __syncthreads();
     }
-    if (tid == 0) {
-        e1 = red[0][0];
-        e2 = red[1][0];
-        e12 = red[2][0];
-        en = red[3][0];
-        const double g2 = e2 > 0.0 ? sqrt(e1 / (e2 * exp10(static_cast<double>(sir_db[b]) / 10.0))) : 0.0;
-        const double esp = e1 + 2.0 * g2 * e12 + g2 * g2 * e2;
-        const double gn = en > 0.0 ? sqrt(esp / (en * exp10(static_cast<double>(snr_db[b]) / 10.0))) : 0.0;
-        float* g = gains + R.src0;
-        g[0] = 1.0f;
-        g[1] = static_cast<float>(g2);
-        g[2] = static_cast<float>(gn);
-    }
+    if (tid < 4) partials[(static_cast<int64_t>(b) * kEnergyParts + part) * 4 + tid] = red[tid][0];
+}
+
+// Per room: the partial energies summed in part order, then the gains
+// (1, g2, gn) of the room's SIR and SNR (a silent source gets gain 0).
+__global__ void spatial_gain_kernel(const void* __restrict__ desc, const double* __restrict__ partials,
+                                    const float* __restrict__ sir_db, const float* __restrict__ snr_db,
+                                    float* __restrict__ gains, int n_rooms) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_rooms) return;
+    const RoomDesc& R = rooms(desc)[b];
+    double e[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* pb = partials + static_cast<int64_t>(b) * kEnergyParts * 4;
+    for (int p = 0; p < kEnergyParts; ++p)
+        for (int q = 0; q < 4; ++q) e[q] += pb[4 * p + q];
+    const double e1 = e[0], e2 = e[1], e12 = e[2], en = e[3];
+    const double g2 = e2 > 0.0 ? sqrt(e1 / (e2 * exp10(static_cast<double>(sir_db[b]) / 10.0))) : 0.0;
+    const double esp = e1 + 2.0 * g2 * e12 + g2 * g2 * e2;
+    const double gn = en > 0.0 ? sqrt(esp / (en * exp10(static_cast<double>(snr_db[b]) / 10.0))) : 0.0;
+    gains[R.src0] = 1.0f;
+    gains[R.src0 + 1] = static_cast<float>(g2);
+    gains[R.src0 + 2] = static_cast<float>(gn);
 }
 
 // Scaled images (in place) and the mixture; blocks (chunk, room).
@@ -255,7 +306,7 @@ __global__ void spatial_mix_kernel(const void* __restrict__ desc, float* __restr
 
 struct SpatialLayout {
     int tm, adv, n_blk;
-    int64_t tw_off, rt_off, h_off, x_off, bytes;
+    int64_t tw_off, rt_off, h_off, x_off, e_off, bytes;
 };
 
 int spatial_layout(const framrir_plan* plan, int32_t n_samples, SpatialLayout& L) {
@@ -277,7 +328,8 @@ int spatial_layout(const framrir_plan* plan, int32_t n_samples, SpatialLayout& L
     L.rt_off = align(L.tw_off + 8 * static_cast<int64_t>(kFftN));
     L.h_off = align(L.rt_off + 8 * static_cast<int64_t>(kBins));
     L.x_off = align(L.h_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_chan);
-    L.bytes = align(L.x_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_src * L.n_blk);
+    L.e_off = align(L.x_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_src * L.n_blk);
+    L.bytes = align(L.e_off + 8 * 4 * static_cast<int64_t>(kEnergyParts) * plan->header.n_rooms);
     return FRAMRIR_OK;
 }
 
@@ -343,8 +395,12 @@ extern "C" int framrir_spatialize(const framrir_plan* plan, const void* desc_dev
     hipLaunchKernelGGL(conv_block_kernel, dim3(n_chan * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev, tw, rt,
                        hspec, xspec, images_dev, L.n_blk, L.adv, L.tm, n_samples);
     if (int rc = check("conv_block_kernel")) return rc;
-    hipLaunchKernelGGL(spatial_gain_kernel, dim3(n_rooms), dim3(kFftThreads), 0, st, desc_dev, images_dev, sir_db_dev,
-                       snr_db_dev, gains_dev, n_samples);
+    double* partials = reinterpret_cast<double*>(w + L.e_off);
+    hipLaunchKernelGGL(spatial_energy_kernel, dim3(kEnergyParts, n_rooms), dim3(kEnergyThreads), 0, st, desc_dev,
+                       images_dev, partials, n_samples);
+    if (int rc = check("spatial_energy_kernel")) return rc;
+    hipLaunchKernelGGL(spatial_gain_kernel, dim3((n_rooms + 63) / 64), dim3(64), 0, st, desc_dev, partials, sir_db_dev,
+                       snr_db_dev, gains_dev, n_rooms);
     if (int rc = check("spatial_gain_kernel")) return rc;
     int max_per = 0;
     for (const RoomDesc& R : plan->rooms) max_per = std::max(max_per, R.n_mic);
