@@ -13,8 +13,8 @@ philox   Philox-4xW-10 counter-based generator, written from its publication.
 cbrt     Correctly rounded FP64 cube root by exact integer arithmetic.
 framrir  The method itself: room scalars (Eq. 2, 5), image draws (Sec. III-B,
          III-C, Eq. 3, 4, 6), band-limited rendering of Eq. 1 / Eq. 8, the
-         adjoint with the draws held fixed, finite differences, and the
-         early-reverberation filter (Eq. 9).
+         adjoints with the draws held fixed and through the draws, finite
+         differences, and the early-reverberation filter (Eq. 9).
 multirate  The paper-literal rendering: high-rate impulses (Eq. 7, 8),
          down-sampling, the 80 Hz high-pass and the second down-sampling
          (Sec. II).

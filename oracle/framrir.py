@@ -411,6 +411,91 @@ def fd_grads(plan, room, target, step=1e-6, mic=None, src=None, r=None):
     return g_mic, g_src, g_r
 
 
+def adjoint_room_draws(plan, room, grad_h, prm):
+    """dL/dmic, dL/dsrc, dL/dr of the whole map, the images re-drawn at the
+    inputs: the Philox variates (theta, phi, xhat, p) depend on the seed only,
+    while with t_i = (xhat_i - alpha)/(beta - alpha) (Eq. 4)
+      D_i = d0 + t_i (cT - d0),  DR_i = D_i / d0,  pos_i = centre + D_i dir_i,
+      g_i = clamp(gamma_i, 1, RR),  gamma_i = 1 + (D_i/cT)^2 (RR - 1) + p_i DR_i^tau,
+      RR = max(1, (log10 cT - log10 d0 - 3) / log10 r)  (Eq. 5, 6),
+      d0 = |src - centre|,  centre = mean of the microphones.
+    Per image the pairs give dL/dpos_i (minus the microphone term) and dL/dg_i
+    = ln(r) A S0; then
+      dL/dd0 = sum_i (dir_i . dL/dpos_i)(1 - t_i) + dL/dg_i dg_i/dd0,
+      dg/dd0 = 2 (D/cT^2)(RR - 1)(1 - t) + (D/cT)^2 dRR/dd0 - tau p DR^(tau-1) t cT / d0^2
+               inside the clamp, dRR/dd0 at the top clamp, 0 at the bottom,
+      dRR/dd0 = -1 / (d0 ln r),  dRR/dr = -RR / (r ln r)  (0 where RR is clamped to 1),
+      dL/dsrc += dL/dd0 (src - centre) / d0,
+      dL/dmic += (sum_i dL/dpos_i - dL/dd0 (src - centre) / d0) / M  (every microphone),
+      dL/dr += sum_i dL/dg_i dg_i/dr  (dg/dr = (D/cT)^2 dRR/dr inside, dRR/dr at the top).
+    Gradient at the room's own positions (where the images were drawn)."""
+    g_mic, g_src, g_r = adjoint_room(plan, room, grad_h)
+    r, centre, fs, c, t_len = plan["r"], plan["centre"], room.fs, room.c, plan["T"]
+    ln_r = math.log(r)
+    n_mic = len(room.mic)
+    g_centre = np.zeros(3)
+    for s, so in enumerate(plan["sources"]):
+        d = so["draws"]
+        d0, ct, rr = so["d0"], so["ct"], so["rrmax"]
+        pos, g = so["pos"][1:], so["g"][1:]
+        dpos = np.zeros_like(pos)
+        dg = np.zeros(len(g))
+        for m in range(n_mic):
+            diff, dist, t, amp = pair_geometry(pos, g, room.mic[m], r, fs, c)
+            u = diff / dist[:, None]
+            n, x = footprint(t)
+            ok = (n >= 0) & (n < t_len)
+            gn = np.where(ok, grad_h[s, m][np.clip(n, 0, t_len - 1).astype(np.int64)], 0.0)
+            s0 = np.sum(gn * pulse(x), axis=1)
+            s1 = np.sum(gn * pulse_deriv(x), axis=1)
+            coef = amp / dist * s0 + amp * (fs / c) * s1
+            dpos -= u * coef[:, None]
+            dg += ln_r * amp * s0
+        tt = (d["xhat"] - prm.alpha) / (prm.beta - prm.alpha)
+        D, DR, p = d["dist"], d["dr"], d["p"]
+        rr_raw = ((math.log10(ct) - math.log10(d0)) - 3.0) / math.log10(r)
+        drr_dd0 = -1.0 / (d0 * ln_r) if rr_raw > 1.0 else 0.0
+        drr_dr = -rr_raw / (r * ln_r) if rr_raw > 1.0 else 0.0
+        gamma = 1.0 + (D / ct) ** 2 * (rr - 1.0) + p * DR ** prm.tau
+        dgam_dd0 = (2.0 * D / ct ** 2 * (rr - 1.0) * (1.0 - tt) + (D / ct) ** 2 * drr_dd0
+                    - prm.tau * p * DR ** (prm.tau - 1.0) * tt * ct / d0 ** 2)
+        dgam_dr = (D / ct) ** 2 * drr_dr
+        top, bottom = gamma >= rr, gamma <= 1.0
+        dg_dd0 = np.where(top, drr_dd0, np.where(bottom, 0.0, dgam_dd0))
+        dg_dr = np.where(top, drr_dr, np.where(bottom, 0.0, dgam_dr))
+        dl_dd0 = float(np.sum(np.sum(d["dir"] * dpos, axis=1) * (1.0 - tt) + dg * dg_dd0))
+        g_r += float(np.sum(dg * dg_dr))
+        u0 = (np.asarray(room.src[s], dtype=np.float64) - centre) / d0
+        g_src[s] += dl_dd0 * u0
+        g_centre += dpos.sum(axis=0) - dl_dd0 * u0
+    g_mic += g_centre[None, :] / n_mic
+    return g_mic, g_src, g_r
+
+
+def fd_grads_draws(room, prm, grad_h, step=1e-6):
+    """Central finite differences of L = sum(grad_h * h) with the images
+    re-drawn at every perturbed input (same seed), r given as an override."""
+    base = room_plan(room, prm)
+
+    def loss(mic, src, r):
+        rm = Room(room.size, room.rt60, room.fs, room.c, room.seed, src, mic, r)
+        return float(np.sum(grad_h * render_room(room_plan(rm, prm), rm)))
+
+    mic, src, r = room.mic.copy(), room.src.copy(), base["r"]
+    g_mic, g_src = np.zeros_like(mic), np.zeros_like(src)
+    for arr, out in ((mic, g_mic), (src, g_src)):
+        for i in range(arr.shape[0]):
+            for k in range(3):
+                plus, minus = arr.copy(), arr.copy()
+                plus[i, k] += step
+                minus[i, k] -= step
+                lp = loss(plus, src, r) if arr is mic else loss(mic, plus, r)
+                lm = loss(minus, src, r) if arr is mic else loss(mic, minus, r)
+                out[i, k] = (lp - lm) / (2 * step)
+    g_r = (loss(mic, src, r + step) - loss(mic, src, r - step)) / (2 * step)
+    return g_mic, g_src, g_r
+
+
 # ---------------------------------------------------------------------------
 # Early-reverberation mask (Eq. 9), at the output rate
 # ---------------------------------------------------------------------------

@@ -255,6 +255,20 @@ def spatial_signals(batch, n_samples, seed=0):
     return sig, sir, snr
 
 
+def t60_curriculum_range(epoch, t60_max):
+    """T60 range (seconds) for a training epoch (0-based) under the T60
+    curriculum of Sec. V: [0.05, 0.10] s at the first epoch, the upper bound
+    raised by 0.05 s per epoch until it reaches t60_max."""
+    hi = min(t60_max, 0.10 + 0.05 * epoch)
+    return 0.05, max(0.05, hi)
+
+
+def t60_curriculum_sample(epoch, t60_max, n, seed=0):
+    """n T60 values drawn uniformly from the epoch's curriculum range (seeded)."""
+    lo, hi = t60_curriculum_range(epoch, t60_max)
+    return np.random.default_rng([4000, seed, epoch]).uniform(lo, hi, n)
+
+
 def upstream_grad(shape_total, seed=0):
     """Seeded N(0, 1) FP32 upstream gradient for backward benchmarks."""
     rng = np.random.default_rng([3000, seed])

@@ -206,3 +206,15 @@ def test_early_layout_matches_oracle(maker):
         chan += len(rm.src) * len(rm.mic)
     assert plan.early_off[-1] == off == plan.info.early_floats
     assert plan.chan_off[-1] == chan == plan.info.n_chan
+
+
+def test_t60_curriculum_schedule():
+    """Sec. V: the range starts at [50, 100] ms and its upper bound grows by
+    50 ms per epoch until the maximum T60."""
+    assert W.t60_curriculum_range(0, 0.7) == (0.05, 0.10)
+    assert np.allclose(W.t60_curriculum_range(1, 0.7), (0.05, 0.15))
+    assert np.allclose(W.t60_curriculum_range(11, 0.7), (0.05, 0.65))
+    assert W.t60_curriculum_range(12, 0.7) == (0.05, 0.7)
+    assert W.t60_curriculum_range(40, 0.7) == (0.05, 0.7)
+    x = W.t60_curriculum_sample(3, 0.7, 1000, seed=1)
+    assert np.all((x >= 0.05) & (x <= 0.25)) and np.array_equal(x, W.t60_curriculum_sample(3, 0.7, 1000, seed=1))

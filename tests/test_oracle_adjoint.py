@@ -1,8 +1,11 @@
-"""Pins of the oracle's adjoint (gradients with the draws held fixed, reading
-R-20) against FP64 central finite differences of the rendered loss."""
+"""Pins of the oracle's adjoints against FP64 central finite differences:
+with the draws held fixed (reading R-20), and through the draws (the images
+re-drawn at the inputs from the same seed)."""
 import numpy as np
+import pytest
 
 from oracle import framrir as F
+from paper_2304_08052_amd import workloads as W
 
 
 def _setup(n_img=30, n_mic=3, rt60=0.12, fs=16000.0):
@@ -60,3 +63,27 @@ def test_pulse_derivative_matches_difference_quotient():
     assert np.max(np.abs(F.pulse_deriv(x) - fd)) < 1e-8
     # C^1 at the footprint edge
     assert abs(F.pulse(40.5)) < 1e-15 and abs(F.pulse_deriv(40.4999999)) < 1e-9
+
+
+@pytest.mark.parametrize("tau", [0.25, 0.5, 1.0])
+def test_adjoint_through_draws_matches_fd(tau):
+    """The gradient through the draws (images re-drawn at the inputs, the
+    Philox variates fixed by the seed) against central finite differences of
+    the whole pipeline; the rooms include rows at both clamps of Eq. 6."""
+    prm = F.Params(img_lo=200, img_hi=400, tau=tau)
+    batch = W.config4(2)
+    clamped = [0, 0]
+    for b, rm in enumerate(F.rooms_from_batch(batch)):
+        op = F.room_plan(rm, prm)
+        for so in op["sources"]:
+            d = so["draws"]
+            gam = 1.0 + (d["dist"] / so["ct"]) ** 2 * (so["rrmax"] - 1.0) + d["p"] * d["dr"] ** tau
+            clamped[0] += int(np.sum(gam <= 1.0))
+            clamped[1] += int(np.sum(gam >= so["rrmax"]))
+        G = np.random.default_rng(b).standard_normal((len(rm.src), len(rm.mic), op["T"]))
+        gm, gs, gr = F.adjoint_room_draws(op, rm, G, prm)
+        fm, fs_, fr_ = F.fd_grads_draws(rm, prm, G, step=1e-6)
+        assert np.linalg.norm(gm - fm) / np.linalg.norm(fm) < 1e-6
+        assert np.linalg.norm(gs - fs_) / np.linalg.norm(fs_) < 1e-6
+        assert abs(gr - fr_) / abs(fr_) < 1e-6
+    assert clamped[0] > 0 and clamped[1] > 0
