@@ -7,8 +7,9 @@ table) and the render (RIRs) -- forward; the backward step adds the adjoint.
 The headline workload is the batched forward: 256 rooms, 2 sources each,
 6-microphone circular arrays, 16 kHz.
 
-Prints ONE JSON line (rank 0).  Extra fields: forward+backward time and its
-ratio to the forward, eager vs hipGraph step times, the host planning time.
+Prints ONE JSON line (rank 0).  Extra fields: forward+backward time (draws
+held fixed, and through the draws) and its ratio to the forward, eager vs
+hipGraph step times, the host planning time.
 """
 import argparse
 import json
@@ -269,6 +270,22 @@ def main():
         torch.cuda.synchronize()
         fb_ms = t_start.elapsed_time(t_end) / args.steps
 
+    # ---- forward + backward through the draws (images moving with the inputs)
+    fbd_ms = None
+    if not args.no_backward:
+        def bwd_draws_step():
+            fwd_step()
+            plan.backward_draws(table, grad, ws=ws, prepared=True)
+        for _ in range(max(1, args.warmup // 2)):
+            bwd_draws_step()
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for _ in range(args.steps):
+            bwd_draws_step()
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        fbd_ms = t_start.elapsed_time(t_end) / args.steps
+
     early_ms = None
     if args.early:
         early_buf, start_buf = plan.early(out)
@@ -356,6 +373,7 @@ def main():
         "graph_ms_per_step": graph_ms,
         "fwd_bwd_ms_per_step": fb_ms,
         "fwd_bwd_over_fwd": (fb_ms / eager_ms) if fb_ms else None,
+        "fwd_bwd_draws_ms_per_step": fbd_ms,
         "per_room_ms_per_step": per_room_ms,
         "early_ms": early_ms,
         "plan_host_ms": plan_ms,

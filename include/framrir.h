@@ -261,6 +261,38 @@ int framrir_render_backward_prepared(const framrir_plan* plan, const void* desc_
                                      float* grad_src_dev, float* grad_r_dev, void* ws_dev, size_t ws_bytes,
                                      void* stream);
 
+/* Gradient through the draws: the images move with the inputs.  The
+ * Philox variates of every image (direction, x-hat, p) stay fixed, while d0 =
+ * |src - centre| (centre = mean of the room's microphones), RR_max (Eq. 5)
+ * and through them each image's distance D_i = d0 + t_i (c0 T60 - d0) (Eq. 4,
+ * t_i = (x-hat_i - alpha) / (beta - alpha)), position centre + D_i dir_i and
+ * reflection count g_i = clamp(gamma_i, 1, RR_max) (Eq. 6) follow src, the
+ * microphones and r.  To the terms of framrir_render_backward this adds, per
+ * source s and with dL/dpos_i the image's own gradient:
+ *   dL/dd0   = sum_i (dir_i . dL/dpos_i)(1 - t_i) + ln(r) A S0 dg_i/dd0,
+ *   dL/dsrc_s += dL/dd0 (src_s - centre) / d0,
+ *   dL/dmic_m += (sum_i dL/dpos_i - dL/dd0 (src_s - centre) / d0) / M,
+ *   dL/dr_b   += sum_i ln(r) A S0 dg_i/dr,
+ * with dg/dd0, dg/dr from Eq. 5-6 inside the clamp, dRR_max/dd0 and
+ * dRR_max/dr on the top clamp and 0 on the bottom one.  p DR_i^tau is
+ * recovered from the row's reflection count (FP32 in the prepared rows).
+ * The gradient is taken where the table was drawn: table_dev must hold
+ * framrir_draw's rows for this plan, and mic_dev and src_dev the positions
+ * the plan was made with; r is the plan's (no override).  Outputs, workspace,
+ * order of the sums and errors as for framrir_render_backward; the direct
+ * path (row 0) contributes as there. */
+int framrir_render_backward_draws(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
+                                  const double* mic_dev, const double* src_dev, const float* grad_out_dev,
+                                  float* grad_mic_dev, float* grad_src_dev, float* grad_r_dev, void* ws_dev,
+                                  size_t ws_bytes, void* stream);
+
+/* framrir_render_backward_draws reusing a preparation already in ws_dev: the
+ * one a framrir_forward / framrir_prepare call with r_dev = NULL left for the
+ * same plan, table and the plan's own positions. */
+int framrir_render_backward_draws_prepared(const framrir_plan* plan, const void* desc_dev, const double* mic_dev,
+                                           const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
+                                           float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Early-reverberation filter of Eq. 9, at the output rate: for every
  * (source s, mic m) channel, t0 = |src_s - mic_m| fs / c0 (FP64, correctly
  * rounded square root, then one multiply and one divide) and the window

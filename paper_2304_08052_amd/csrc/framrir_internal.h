@@ -28,7 +28,11 @@ constexpr int kPool = 128;         // render: pairs a wave ranks by bank per rou
 // above: per wave the staged pool (3 words per pair) and the bank counts,
 // plus the microphone group and the item slot.
 constexpr int render_static_lds(int nt) { return 512 + (nt / 64) * (3 * kPool + kLdsBanks) * 4; }
-constexpr int kPartialStride = 3 * kMaxMicGroup + 4;   // backward partials per item
+// Backward partials per item: dL/dmic per microphone of the group (3 each),
+// then dL/dsrc through the direct path (3), dL/dr, and for the gradient
+// through the draws the sum of dL/dpos over the item's images (3) and dL/dd0.
+constexpr int kPartialStride = 3 * kMaxMicGroup + 8;
+constexpr int kPartSrc = 3 * kMaxMicGroup, kPartR = kPartSrc + 3, kPartPos = kPartR + 1, kPartD0 = kPartPos + 3;
 
 enum TauCode : int32_t { kTauQuarter = 0, kTauHalf = 1, kTauOne = 2 };
 

@@ -9,7 +9,8 @@
 //                    an FP64 delay, then 81 windowed-sinc taps accumulated in an
 //                    LDS tile as fixed-point integers (ds_add_u32) under a
 //                    per-source scale that cannot overflow; coalesced writeback.
-//   backward_kernel  adjoint of the render with the image table held fixed:
+//   backward_kernel  adjoint of the render with the image table held fixed
+//                    (or, DRAWS, with the images moving with the inputs):
 //                    per pair 81-tap dot products of dL/dh with P and P', and
 //                    the fixed-order reduction of each room's partials.
 //
@@ -977,8 +978,13 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
 // ---------------------------------------------------------------------------
 // Sums the partials of room b's items in the plan's fixed order (room_items)
 // into its gradient outputs.  scratch: at least 4 ints of LDS, staging the
-// item table in chunks so that the partial loads do not chain.
-template <int NT>
+// item table in chunks so that the partial loads do not chain.  DRAWS adds
+// the terms through the draws (Eq. 4-6): with u0_s = (src_s - centre) / d0_s
+// and dL/dd0_s the sum of the items' dL/dd0 partials,
+//   dL/dsrc_s += dL/dd0_s u0_s,
+//   dL/dmic_m += sum over the room's items of (sum dL/dpos - dL/dd0 u0_s) / M,
+// the centre being the mean of the M microphones.
+template <int NT, bool DRAWS>
 __device__ void finalize_room(const void* __restrict__ desc, int b, const float* __restrict__ partials,
                               float* __restrict__ grad_mic, float* __restrict__ grad_src, float* __restrict__ grad_r,
                               int* __restrict__ scratch, int scratch_words) {
@@ -990,7 +996,8 @@ __device__ void finalize_room(const void* __restrict__ desc, int b, const float*
     const int chunk = scratch_words / 4;
     for (int ob = 0; ob < n_out; ob += NT) {
         const int o = ob + static_cast<int>(threadIdx.x);
-        float sum = 0.0f;
+        const int axis = o % 3;
+        float sum = 0.0f, extra = 0.0f;   // extra: the centre term (microphones) or dL/dd0 (sources)
         for (int j0 = 0; j0 < R->n_item; j0 += chunk) {
             const int nj = min(chunk, R->n_item - j0);
             __syncthreads();
@@ -1007,23 +1014,36 @@ __device__ void finalize_room(const void* __restrict__ desc, int b, const float*
                 for (int j = 0; j < nj; ++j) {
                     const int id = scratch[4 * j], mic0 = scratch[4 * j + 1], nm = scratch[4 * j + 2],
                               sl = scratch[4 * j + 3];
+                    const float* part = partials + static_cast<int64_t>(id) * kPartialStride;
                     int at;   // this item's partial feeding output o, or -1
                     if (o < n_mic3) {
                         const int m = o / 3 - mic0;
-                        at = (m >= 0 && m < nm) ? m * 3 + o % 3 : -1;
+                        at = (m >= 0 && m < nm) ? m * 3 + axis : -1;
+                        if (DRAWS) {
+                            const SrcDesc* S = srcs(desc) + R->src0 + sl;
+                            const float u0 = static_cast<float>((S->pos[axis] - R->centre[axis]) / S->d0);
+                            extra += part[kPartPos + axis] - part[kPartD0] * u0;
+                        }
                     } else if (o < n_mic3 + n_src3) {
-                        at = ((o - n_mic3) / 3 == sl) ? 3 * kMaxMicGroup + (o - n_mic3) % 3 : -1;
+                        const bool mine = (o - n_mic3) / 3 == sl;
+                        at = mine ? kPartSrc + axis : -1;
+                        if (DRAWS && mine) extra += part[kPartD0];
                     } else {
-                        at = 3 * kMaxMicGroup + 3;
+                        at = kPartR;
                     }
-                    const float v = partials[static_cast<int64_t>(id) * kPartialStride + max(at, 0)];
+                    const float v = part[max(at, 0)];
                     sum += at >= 0 ? v : 0.0f;
                 }
             }
         }
         if (o < n_mic3) {
+            if (DRAWS) sum += extra / static_cast<float>(R->n_mic);
             if (grad_mic) grad_mic[3 * R->mic0 + o] = sum;
         } else if (o < n_mic3 + n_src3) {
+            if (DRAWS) {
+                const SrcDesc* S = srcs(desc) + R->src0 + (o - n_mic3) / 3;
+                sum += extra * static_cast<float>((S->pos[axis] - R->centre[axis]) / S->d0);
+            }
             if (grad_src) grad_src[3 * R->src0 + (o - n_mic3)] = sum;
         } else if (o < n_out) {
             if (grad_r) grad_r[b] = sum;
@@ -1036,8 +1056,23 @@ __device__ void finalize_room(const void* __restrict__ desc, int b, const float*
 // it; per-thread sums reduce in a fixed two-stage order into the item's
 // partials.  The last item of a room to finish (a per-room count) sums the
 // room's partials in the plan's order, so the gradients are bitwise
-// reproducible whatever the schedule.  Dynamic LDS: max(tile, 8 NT floats).
-template <int NT, int WPE>
+// reproducible whatever the schedule.  Dynamic LDS: max(tile, (NV + 1) NT
+// floats), NV = bwd_values(DRAWS).
+//
+// DRAWS: the images move with the inputs (Eq. 4-6, the Philox variates held
+// fixed).  Image i sits at centre + D_i dir_i with D_i = d0 + t_i (cT - d0),
+// so with w = dL/dpos_i of a pair (minus the microphone's term) each pair also
+// adds w to the item's position sum and (dir_i . w)(1 - t_i) + dL/dg_i
+// dg_i/dd0 to its dL/dd0, dL/dg_i = ln(r) s0, and dL/dg_i dg_i/dr to dL/dr.
+// dg/dd0 and dg/dr follow Eq. 6 with RR = RR_max(d0, r) of Eq. 5: inside the
+// clamp 2 (D/cT^2)(RR - 1)(1 - t) + (D/cT)^2 dRR/dd0 - tau p DR^tau t cT /
+// (D d0) and (D/cT)^2 dRR/dr, where p DR^tau = g - 1 - (D/cT)^2 (RR - 1) is
+// recovered from the row's g; dRR/dd0 and dRR/dr on the top clamp (g = RR),
+// 0 on the bottom one (g = 1).  The direct path (row 0) does not move this way.
+template <bool DRAWS>
+constexpr int bwd_values() { return DRAWS ? 11 : 7; }
+
+template <int NT, int WPE, bool DRAWS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, const double* __restrict__ r_in,
                 const float* __restrict__ gout, const double* __restrict__ sorted, const int* __restrict__ bucket_off,
@@ -1090,6 +1125,25 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
         const float fsc = static_cast<float>(c.fs_over_c);
         const float inv_r = static_cast<float>(1.0 / c.r);
         float gmx = 0.f, gmy = 0.f, gmz = 0.f, gsx = 0.f, gsy = 0.f, gsz = 0.f, gr = 0.f;
+        // through the draws: per-source constants and the sums over images
+        float wx = 0.f, wy = 0.f, wz = 0.f, gd0 = 0.f;
+        float d0f = 0.f, inv_span = 0.f, inv_ct = 0.f, rrm1 = 0.f, lnr = 0.f, drr_dd0 = 0.f, drr_dr = 0.f,
+              rrf = 0.f, tau_ct_d0 = 0.f;
+        if (DRAWS) {
+            const SrcDesc* S = srcs(desc) + c.w.src;
+            const double ln_r = log(c.r);
+            const bool rr_free = S->rrmax > 1.0;   // RR_max not clamped to 1
+            d0f = static_cast<float>(S->d0);
+            inv_span = static_cast<float>(1.0 / (S->ct - S->d0));
+            inv_ct = static_cast<float>(1.0 / S->ct);
+            rrf = static_cast<float>(S->rrmax);
+            rrm1 = static_cast<float>(S->rrmax - 1.0);
+            lnr = static_cast<float>(ln_r);
+            drr_dd0 = rr_free ? static_cast<float>(-1.0 / (S->d0 * ln_r)) : 0.f;
+            drr_dr = rr_free ? static_cast<float>(-S->rrmax / (c.r * ln_r)) : 0.f;
+            const double tau = H->tau_code == kTauQuarter ? 0.25 : H->tau_code == kTauHalf ? 0.5 : 1.0;
+            tau_ct_d0 = static_cast<float>(tau * S->ct / S->d0);
+        }
         __syncthreads();
         if (my_slot < ipp && my_slot < n_list) {
             int e = my_slot;
@@ -1116,28 +1170,61 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
                 gmx = __builtin_fmaf(P.ux, q, gmx);
                 gmy = __builtin_fmaf(P.uy, q, gmy);
                 gmz = __builtin_fmaf(P.uz, q, gmz);
+                const float g = render_row_g(cur.w);
                 if (ce == row0) {
                     gsx -= P.ux * q;
                     gsy -= P.uy * q;
                     gsz -= P.uz * q;
+                } else if (DRAWS) {
+                    const float ex = static_cast<float>(cur.x - c.cx), ey = static_cast<float>(cur.y - c.cy),
+                                ez = static_cast<float>(cur.z - c.cz);
+                    const float Dc = __builtin_sqrtf(ex * ex + ey * ey + ez * ez);
+                    const float t = (Dc - d0f) * inv_span;
+                    // dir . dL/dpos = -q (u . (pos - centre)) / D
+                    const float wd = -q * ((P.ux * ex + P.uy * ey + P.uz * ez) / Dc);
+                    wx -= P.ux * q;
+                    wy -= P.uy * q;
+                    wz -= P.uz * q;
+                    float dg_dd0 = 0.f, dg_dr = 0.f;
+                    if (g >= rrf) {
+                        dg_dd0 = drr_dd0;
+                        dg_dr = drr_dr;
+                    } else if (g > 1.0f) {
+                        const float sr = Dc * inv_ct;                      // D / cT
+                        const float pdr = (g - 1.0f) - (sr * sr) * rrm1;   // p DR^tau
+                        dg_dd0 = 2.0f * sr * inv_ct * rrm1 * (1.0f - t) + (sr * sr) * drr_dd0 -
+                                 tau_ct_d0 * pdr * t / Dc;
+                        dg_dr = (sr * sr) * drr_dr;
+                    }
+                    const float lg = lnr * s0;   // dL/dg of the pair
+                    gd0 += wd * (1.0f - t) + lg * dg_dd0;
+                    gr = __builtin_fmaf(lg, dg_dr, gr);
                 }
-                gr = __builtin_fmaf(render_row_g(cur.w) * inv_r, s0, gr);
+                gr = __builtin_fmaf(g * inv_r, s0, gr);
             }
         }
         __syncthreads();
         // two-stage fixed-order reduction.  Tasks: (microphone, axis) over
-        // the slots of that microphone, then source (3 axes) and r over all
-        // threads; each task in NC chunks, then the chunk sums in order.
-        float* red = tile;                 // NT x 7
-        float* red2 = tile + 7 * NT;       // n_task x NC
-        red[tid * 7 + 0] = gmx;
-        red[tid * 7 + 1] = gmy;
-        red[tid * 7 + 2] = gmz;
-        red[tid * 7 + 3] = gsx;
-        red[tid * 7 + 4] = gsy;
-        red[tid * 7 + 5] = gsz;
-        red[tid * 7 + 6] = gr;
-        const int n_task = 3 * mg + 4;
+        // the slots of that microphone, then source (3 axes), r and (DRAWS)
+        // the position sum (3 axes) and dL/dd0 over all threads; each task in
+        // NC chunks, then the chunk sums in order.
+        constexpr int NV = bwd_values<DRAWS>();
+        float* red = tile;                 // NT x NV
+        float* red2 = tile + NV * NT;      // n_task x NC
+        red[tid * NV + 0] = gmx;
+        red[tid * NV + 1] = gmy;
+        red[tid * NV + 2] = gmz;
+        red[tid * NV + 3] = gsx;
+        red[tid * NV + 4] = gsy;
+        red[tid * NV + 5] = gsz;
+        red[tid * NV + 6] = gr;
+        if (DRAWS) {
+            red[tid * NV + 7] = wx;
+            red[tid * NV + 8] = wy;
+            red[tid * NV + 9] = wz;
+            red[tid * NV + 10] = gd0;
+        }
+        const int n_task = 3 * mg + NV - 3;
         const int NC = max(1, min(NT / n_task, NT / 8));
         __syncthreads();
         if (tid < n_task * NC) {
@@ -1146,11 +1233,11 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
             if (task < 3 * mg) {            // microphone task: threads slot * mg + m
                 const int m = task / 3, k = task % 3;
                 const int s_lo = (ipp * ch) / NC, s_hi = (ipp * (ch + 1)) / NC;
-                for (int sl = s_lo; sl < s_hi; ++sl) sum += red[(sl * mg + m) * 7 + k];
-            } else {                        // source / r task: every thread
+                for (int sl = s_lo; sl < s_hi; ++sl) sum += red[(sl * mg + m) * NV + k];
+            } else {                        // per-item tasks: every thread
                 const int k = 3 + (task - 3 * mg), n = ipp * mg;
                 const int t_lo = (n * ch) / NC, t_hi = (n * (ch + 1)) / NC;
-                for (int t = t_lo; t < t_hi; ++t) sum += red[t * 7 + k];
+                for (int t = t_lo; t < t_hi; ++t) sum += red[t * NV + k];
             }
             red2[tid] = sum;
         }
@@ -1159,7 +1246,7 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
         if (tid < n_task) {
             float sum = 0.f;
             for (int ch = 0; ch < NC; ++ch) sum += red2[tid * NC + ch];
-            part[tid < 3 * mg ? tid : 3 * kMaxMicGroup + (tid - 3 * mg)] = sum;
+            part[tid < 3 * mg ? tid : kPartSrc + (tid - 3 * mg)] = sum;
         }
         // completion of the room: after the barrier one release fence
         // publishes the item's partials and the item is counted; the last
@@ -1174,7 +1261,7 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
         __syncthreads();
         if (s_last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            finalize_room<NT>(desc, c.room, partials, grad_mic, grad_src, grad_r, reinterpret_cast<int*>(tile),
+            finalize_room<NT, DRAWS>(desc, c.room, partials, grad_mic, grad_src, grad_r, reinterpret_cast<int*>(tile),
                               lds_words);
             if (tid == 0) atomicExch(&room_done[c.room], 0);
         }
@@ -1642,10 +1729,37 @@ extern "C" int framrir_forward(const framrir_plan* plan, const void* desc_dev, d
                                    stream);
 }
 
-extern "C" int framrir_render_backward_prepared(const framrir_plan* plan, const void* desc_dev,
-                                                const double* mic_dev, const double* r_dev,
-                                                const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
-                                                float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+namespace {
+
+struct BwdArgs {
+    const void* desc;
+    const double* mic;
+    const double* r;
+    const float* grad_out;
+    const double* sorted;
+    const int* bucket_off;
+    const int* row0_slot;
+    int* room_done;
+    float* partials;
+    int* counters;
+    float* grad_mic;
+    float* grad_src;
+    float* grad_r;
+    int lds_words;
+};
+
+template <int NT, int WPE, bool DRAWS>
+int launch_backward_kernel(dim3 grid, dim3 block, int lds, hipStream_t st, const BwdArgs& a) {
+    if (int rc = allow_lds<backward_kernel<NT, WPE, DRAWS>>()) return rc;
+    hipLaunchKernelGGL((backward_kernel<NT, WPE, DRAWS>), grid, block, lds, st, a.desc, a.mic, a.r, a.grad_out,
+                       a.sorted, a.bucket_off, a.row0_slot, a.room_done, a.partials, a.counters, a.grad_mic,
+                       a.grad_src, a.grad_r, a.lds_words);
+    return FRAMRIR_OK;
+}
+
+int launch_backward(const framrir_plan* plan, const void* desc_dev, const double* mic_dev, const double* r_dev,
+                    const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev, float* grad_r_dev,
+                    void* ws_dev, size_t ws_bytes, hipStream_t st, bool draws) {
     if (plan && plan->header.multirate)
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
     if (!plan || !desc_dev || !mic_dev || !grad_out_dev || !ws_dev)
@@ -1655,27 +1769,41 @@ extern "C" int framrir_render_backward_prepared(const framrir_plan* plan, const 
     if (static_cast<int64_t>(ws_bytes) < plan->ws_bwd_bytes)
         return fr_fail(FRAMRIR_E_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes,
                        static_cast<long long>(plan->ws_bwd_bytes));
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const RenderWs w = render_ws(plan, ws_dev);
     float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + plan->ws_part_off);
     const int nt = plan->launch.bwd_wg_threads;
-    const int lds = std::max(plan->launch.lds_bytes, 32 * nt);
+    const int red_floats = (draws ? bwd_values<true>() : bwd_values<false>()) + 1;
+    const int lds = std::max(plan->launch.lds_bytes, 4 * red_floats * nt);
     const dim3 grid(plan->bwd_grid), block(nt);
-    const int key = nt * 16 + plan->launch.waves_per_simd;
+    // The adjoint through the draws holds 11 sums per thread and runs at 4
+    // waves per SIMD whatever the launch asks (at 8 its registers spill).
+    const int key = nt * 16 + (draws ? 4 : plan->launch.waves_per_simd);
+    const BwdArgs args{desc_dev, mic_dev, r_dev, grad_out_dev, w.sorted, w.bucket_off, w.row0_slot, w.room_done,
+                       partials, w.counters, grad_mic_dev, grad_src_dev, grad_r_dev, lds / 4};
+    int rc = FRAMRIR_OK;
     switch (key) {
-#define FR_CASE(NT, WPE)                                                                                      \
-    case NT * 16 + WPE:                                                                                       \
-        if (int rc2 = allow_lds<backward_kernel<NT, WPE>>()) return rc2;                                        \
-        hipLaunchKernelGGL((backward_kernel<NT, WPE>), grid, block, lds, st, desc_dev, mic_dev, r_dev,       \
-                           grad_out_dev, w.sorted, w.bucket_off, w.row0_slot, w.room_done, partials,          \
-                           w.counters, grad_mic_dev, grad_src_dev, grad_r_dev, lds / 4);                      \
+#define FR_CASE(NT, WPE)                                                                         \
+    case NT * 16 + WPE:                                                                          \
+        rc = (draws && WPE == 4) ? launch_backward_kernel<NT, 4, true>(grid, block, lds, st, args) \
+                                 : launch_backward_kernel<NT, WPE, false>(grid, block, lds, st, args); \
         break;
         FR_KERNEL_SHAPES(FR_CASE)
 #undef FR_CASE
         default:
             return fr_fail(FRAMRIR_E_UNSUPPORTED, "launch shape not compiled");
     }
+    if (rc) return rc;
     return check_launch("backward_kernel");
+}
+
+}  // namespace
+
+extern "C" int framrir_render_backward_prepared(const framrir_plan* plan, const void* desc_dev,
+                                                const double* mic_dev, const double* r_dev,
+                                                const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
+                                                float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    return launch_backward(plan, desc_dev, mic_dev, r_dev, grad_out_dev, grad_mic_dev, grad_src_dev, grad_r_dev,
+                           ws_dev, ws_bytes, static_cast<hipStream_t>(stream), false);
 }
 
 extern "C" int framrir_render_backward(const framrir_plan* plan, const void* desc_dev, const double* table_dev,
@@ -1692,6 +1820,30 @@ extern "C" int framrir_render_backward(const framrir_plan* plan, const void* des
     if (rc) return rc;
     return framrir_render_backward_prepared(plan, desc_dev, mic_dev, r_dev, grad_out_dev, grad_mic_dev,
                                             grad_src_dev, grad_r_dev, ws_dev, ws_bytes, stream);
+}
+
+extern "C" int framrir_render_backward_draws_prepared(const framrir_plan* plan, const void* desc_dev,
+                                                      const double* mic_dev, const float* grad_out_dev,
+                                                      float* grad_mic_dev, float* grad_src_dev, float* grad_r_dev,
+                                                      void* ws_dev, size_t ws_bytes, void* stream) {
+    return launch_backward(plan, desc_dev, mic_dev, nullptr, grad_out_dev, grad_mic_dev, grad_src_dev, grad_r_dev,
+                           ws_dev, ws_bytes, static_cast<hipStream_t>(stream), true);
+}
+
+extern "C" int framrir_render_backward_draws(const framrir_plan* plan, const void* desc_dev,
+                                             const double* table_dev, const double* mic_dev, const double* src_dev,
+                                             const float* grad_out_dev, float* grad_mic_dev, float* grad_src_dev,
+                                             float* grad_r_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (plan && plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, grad_out_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_bwd_bytes : 0);
+    if (rc) return rc;
+    rc = launch_prepare(plan, desc_dev, const_cast<double*>(table_dev), mic_dev, src_dev, nullptr, ws_dev,
+                        static_cast<hipStream_t>(stream), false);
+    if (rc) return rc;
+    return framrir_render_backward_draws_prepared(plan, desc_dev, mic_dev, grad_out_dev, grad_mic_dev, grad_src_dev,
+                                                  grad_r_dev, ws_dev, ws_bytes, stream);
 }
 
 extern "C" int framrir_early(const framrir_plan* plan, const void* desc_dev, const double* mic_dev,

@@ -70,6 +70,9 @@ EXPORTS = {
     "framrir_render_prepared": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_render_backward": (ctypes.c_int, [ctypes.c_void_p] * 11 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_render_backward_prepared": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_render_backward_draws": (ctypes.c_int, [ctypes.c_void_p] * 10 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_render_backward_draws_prepared": (ctypes.c_int,
+                                               [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_workspace_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_plan_get_early": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "framrir_early": (ctypes.c_int, [ctypes.c_void_p] * 8),
@@ -297,6 +300,30 @@ class Plan:
             _check(lib().framrir_render_backward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
                                                  _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws),
                                                  ws.numel(), _stream(stream)))
+        return gm, gs, gr
+
+    def backward_draws(self, table, grad_out, ws=None, grads=None, stream=None, desc=None, prepared=False):
+        """framrir_render_backward_draws (prepared=True: ..._draws_prepared,
+        reusing the preparation of a forward with r = None in ws): the gradient
+        with the images moving with the plan's positions and r."""
+        import torch
+        if prepared and ws is None:
+            raise ValueError("prepared=True needs the workspace the forward ran on")
+        ws = self.workspace(backward=True) if ws is None else ws
+        desc = self.desc if desc is None else desc
+        if grads is None:
+            grads = (torch.empty((self.info.n_mic, 3), dtype=torch.float32, device=self.device),
+                     torch.empty((self.info.n_src, 3), dtype=torch.float32, device=self.device),
+                     torch.empty(self.info.n_rooms, dtype=torch.float32, device=self.device))
+        gm, gs, gr = grads
+        if prepared:
+            _check(lib().framrir_render_backward_draws_prepared(self._h, _ptr(desc), _ptr(self.mic_dev),
+                                                                _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr),
+                                                                _ptr(ws), ws.numel(), _stream(stream)))
+        else:
+            _check(lib().framrir_render_backward_draws(self._h, _ptr(desc), _ptr(table), _ptr(self.mic_dev),
+                                                       _ptr(self.src_dev), _ptr(grad_out), _ptr(gm), _ptr(gs),
+                                                       _ptr(gr), _ptr(ws), ws.numel(), _stream(stream)))
         return gm, gs, gr
 
     def forward_multirate(self, table=None, mic=None, src=None, r=None, inter=None, out=None, ws=None,
