@@ -55,45 +55,118 @@ __global__ void fft_twiddle_kernel(float2* __restrict__ tw, float2* __restrict__
     }
 }
 
+// 4-point forward DFT: X_q = sum_r v_r (-i)^(r q).
+__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d) {
+    const float2 s02 = cadd(a, c), d02 = csub(a, c), s13 = cadd(b, d), d13 = csub(b, d);
+    const float2 jd13 = make_float2(d13.y, -d13.x);   // -i (v1 - v3)
+    a = cadd(s02, s13);
+    b = cadd(d02, jd13);
+    c = csub(s02, s13);
+    d = csub(d02, jd13);
+}
+
+// 16-point forward DFT in registers, natural order in and out: with n = n2 +
+// 4 n1 and k = k1 + 4 k2, X_k = sum_n2 w16^(n2 k1) w4^(n2 k2) sum_n1 x_(n2 +
+// 4 n1) w4^(n1 k1): 4-point DFTs over n1, the twiddles w16^(n2 k1), 4-point
+// DFTs over n2.
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+    constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508978f, h = 0.70710678118654752f;
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    // v[n2 + 4 k1] now holds Y[n2][k1]; multiply by w16^(n2 k1)
+    v[5] = cmul(v[5], make_float2(c1, -s1));     // w16^1
+    v[6] = cmul(v[6], make_float2(h, -h));       // w16^2
+    v[7] = cmul(v[7], make_float2(s1, -c1));     // w16^3
+    v[9] = cmul(v[9], make_float2(h, -h));       // w16^2
+    v[10] = make_float2(v[10].y, -v[10].x);      // w16^4 = -i
+    v[11] = cmul(v[11], make_float2(-h, -h));    // w16^6
+    v[13] = cmul(v[13], make_float2(s1, -c1));   // w16^3
+    v[14] = cmul(v[14], make_float2(-h, -h));    // w16^6
+    v[15] = cmul(v[15], make_float2(-c1, s1));   // w16^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index
+    float2 t;
+    t = v[1], v[1] = v[4], v[4] = t;
+    t = v[2], v[2] = v[8], v[8] = t;
+    t = v[3], v[3] = v[12], v[12] = t;
+    t = v[6], v[6] = v[9], v[9] = t;
+    t = v[7], v[7] = v[13], v[13] = t;
+    t = v[11], v[11] = v[14], v[14] = t;
+}
+
+// w^m = T1[m / 64] T2[m mod 64], w = exp(-2 pi i / kFftN), m < kFftN.
+__device__ __forceinline__ float2 twiddle(const float2* __restrict__ t1, const float2* __restrict__ t2, int m) {
+    return cmul(t1[m >> 6], t2[m & 63]);
+}
+
 // In-place forward DFT of kFftN points in LDS, natural order in and out:
-// radix-4 Stockham passes (stride Ns = 1, 4, ..., N/4).  Butterfly j takes
-// x[j + r N/4] (r = 0..3), multiplied by w^(r k N / (4 Ns)) with k = j mod Ns,
-// and writes its 4-point DFT to (j / Ns) 4 Ns + k + q Ns.  Every thread reads
-// its inputs, the workgroup synchronises, then writes.  a is addressed
-// through pidx; t1, t2 are the twiddle tables in LDS.
-__device__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ t1, const float2* __restrict__ t2) {
-    constexpr int Q = kFftN / 4 / kFftThreads;   // butterflies per thread and pass
+// Stockham passes, three of radix 16 (stride Ns = 1, 16, 256), then one of
+// radix 4 (Ns = 4096).  Butterfly j of a radix-R pass takes x[j + r N/R]
+// (r = 0..R-1), multiplied by w^(r k N / (R Ns)) with k = j mod Ns, and
+// writes its R-point DFT to (j / Ns) R Ns + k + q Ns.  Every thread reads its
+// inputs, the workgroup synchronises, then writes.  a is addressed through
+// pidx; t1, t2 are the twiddle tables in LDS.  In the radix-16 passes the
+// 15 twiddles of a butterfly are products of w^step and w^(4 step) (at most
+// three roundings deep).
+__device__ __forceinline__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ t1, const float2* __restrict__ t2) {
+    static_assert(kFftN == 16 * 16 * 16 * 4 && kFftN / 16 == kFftThreads, "pass plan of the 16384-point FFT");
     const int tid = threadIdx.x;
 #pragma unroll 1
-    for (int shift = 0; shift < 14; shift += 2) {
+    for (int shift = 0; shift < 12; shift += 4) {
         const int Ns = 1 << shift;
+        const int k = tid & (Ns - 1);
+        float2 v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = a[pidx(tid + r * (kFftN / 16))];
+        if (shift > 0) {
+            const int step = k << (10 - shift);   // k N / (16 Ns)
+            float2 w[16];
+            w[1] = twiddle(t1, t2, step);
+            w[4] = twiddle(t1, t2, 4 * step);
+            w[2] = cmul(w[1], w[1]);
+            w[3] = cmul(w[1], w[2]);
+            w[5] = cmul(w[4], w[1]);
+            w[6] = cmul(w[4], w[2]);
+            w[7] = cmul(w[4], w[3]);
+            w[8] = cmul(w[4], w[4]);
+            w[9] = cmul(w[8], w[1]);
+            w[10] = cmul(w[8], w[2]);
+            w[11] = cmul(w[8], w[3]);
+            w[12] = cmul(w[8], w[4]);
+            w[13] = cmul(w[12], w[1]);
+            w[14] = cmul(w[12], w[2]);
+            w[15] = cmul(w[12], w[3]);
+#pragma unroll
+            for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+        }
+        dft16(v);
+        __syncthreads();
+        const int base = ((tid >> shift) << (shift + 4)) + k;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[pidx(base + q * Ns)] = v[q];
+        __syncthreads();
+    }
+    {   // radix 4, Ns = 4096: butterflies j = tid + 1024 q
+        constexpr int Q = kFftN / 4 / kFftThreads, shift = 12, Ns = 1 << shift;
         float2 v[Q][4];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int j = tid + q * kFftThreads;
-            const int k = j & (Ns - 1);
-            const int step = k << (12 - shift);   // k N / (4 Ns)
+            const int k = j & (Ns - 1);   // step = k N / (4 Ns) = k
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[q][r] = a[pidx(j + r * (kFftN / 4))];
 #pragma unroll
-            for (int r = 1; r < 4; ++r) {
-                const int m = r * step;
-                v[q][r] = cmul(v[q][r], cmul(t1[m >> 6], t2[m & 63]));
-            }
+            for (int r = 1; r < 4; ++r) v[q][r] = cmul(v[q][r], twiddle(t1, t2, r * k));
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int j = tid + q * kFftThreads;
-            const int k = j & (Ns - 1);
-            const int base = ((j >> shift) << (shift + 2)) + k;
-            const float2 s02 = cadd(v[q][0], v[q][2]), d02 = csub(v[q][0], v[q][2]);
-            const float2 s13 = cadd(v[q][1], v[q][3]), d13 = csub(v[q][1], v[q][3]);
-            const float2 jd13 = make_float2(d13.y, -d13.x);   // -i (v1 - v3)
-            a[pidx(base)] = cadd(s02, s13);
-            a[pidx(base + Ns)] = cadd(d02, jd13);
-            a[pidx(base + 2 * Ns)] = csub(s02, s13);
-            a[pidx(base + 3 * Ns)] = csub(d02, jd13);
+            const int base = ((j >> shift) << (shift + 2)) + (j & (Ns - 1));
+            dft4(v[q][0], v[q][1], v[q][2], v[q][3]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[pidx(base + r * Ns)] = v[q][r];
         }
         __syncthreads();
     }
