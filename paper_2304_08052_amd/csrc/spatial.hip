@@ -24,14 +24,18 @@ namespace {
 
 constexpr int kFftN = 16384;             // complex points: a real FFT of kFftL samples, two per point
 constexpr int kFftL = 2 * kFftN;
-constexpr int kFftThreads = 1024;
+constexpr int kFftThreads = 512;
 constexpr int kBins = kFftN + 1;         // bins of the real spectrum
-// LDS: the sequence at padded positions i + i / 16 (the Stockham passes'
-// strided writes then rarely meet in a bank), then two twiddle tables:
-// w^m = T1[m / 64] T2[m mod 64], T1[h] = w^(64 h), T2[l] = w^l.
-constexpr int kPadded = kFftN + kFftN / 16;
+// The sequence lives in registers (32 points per thread); LDS carries the
+// exchanges between passes, half of the sequence at a time, at padded
+// positions i + i / 16 (the Stockham passes' strided writes then rarely meet
+// in a bank), followed by two twiddle tables: w^m = T1[m / 64] T2[m mod 64],
+// T1[h] = w^(64 h), T2[l] = w^l.  About 72 KB: two workgroups per CU, so
+// that one's memory transfers overlap the other's passes.
+constexpr int kHalfN = kFftN / 2;
+constexpr int kHalfPadded = kHalfN + kHalfN / 16;
 constexpr int kT1 = kFftN / 64, kT2 = 64;
-constexpr int kFftLds = (kPadded + kT1 + kT2) * 8;
+constexpr int kFftLds = (kHalfPadded + kT1 + kT2) * 8;
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 constexpr int kSpatialSources = 3;       // two speakers and the noise (sources 0, 1, 2 of a room)
 
@@ -100,81 +104,106 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__ t1, const f
     return cmul(t1[m >> 6], t2[m & 63]);
 }
 
-// In-place forward DFT of kFftN points in LDS, natural order in and out:
-// Stockham passes, three of radix 16 (stride Ns = 1, 16, 256), then one of
-// radix 4 (Ns = 4096).  Butterfly j of a radix-R pass takes x[j + r N/R]
-// (r = 0..R-1), multiplied by w^(r k N / (R Ns)) with k = j mod Ns, and
-// writes its R-point DFT to (j / Ns) R Ns + k + q Ns.  Every thread reads its
-// inputs, the workgroup synchronises, then writes.  a is addressed through
-// pidx; t1, t2 are the twiddle tables in LDS.  In the radix-16 passes the
-// 15 twiddles of a butterfly are products of w^step and w^(4 step) (at most
-// three roundings deep).
-__device__ __forceinline__ void fft_lds(float2* __restrict__ a, const float2* __restrict__ t1, const float2* __restrict__ t2) {
-    static_assert(kFftN == 16 * 16 * 16 * 4 && kFftN / 16 == kFftThreads, "pass plan of the 16384-point FFT");
-    const int tid = threadIdx.x;
-#pragma unroll 1
+// The 15 twiddles w^(r step) of a radix-16 butterfly, r = 1..15, as products
+// of w^step and w^(4 step) (at most three roundings deep).
+__device__ __forceinline__ void twiddle16(const float2* __restrict__ t1, const float2* __restrict__ t2, int step,
+                                          float2 (&v)[16]) {
+    float2 w[16];
+    w[1] = twiddle(t1, t2, step);
+    w[4] = twiddle(t1, t2, 4 * step);
+    w[2] = cmul(w[1], w[1]);
+    w[3] = cmul(w[1], w[2]);
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+    w[8] = cmul(w[4], w[4]);
+    w[9] = cmul(w[8], w[1]);
+    w[10] = cmul(w[8], w[2]);
+    w[11] = cmul(w[8], w[3]);
+    w[12] = cmul(w[8], w[4]);
+    w[13] = cmul(w[12], w[1]);
+    w[14] = cmul(w[12], w[2]);
+    w[15] = cmul(w[12], w[3]);
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+}
+
+// Forward DFT of kFftN points, Stockham passes: three of radix 16 (stride
+// Ns = 1, 16, 256), then one of radix 4 (Ns = 4096).  Butterfly j of a
+// radix-R pass takes x[j + r N/R] (r = 0..R-1), multiplied by w^(r k N / (R
+// Ns)) with k = j mod Ns, and its R-point DFT goes to (j / Ns) R Ns + k + q
+// Ns.  Thread t runs butterflies t and t + 512 of each radix-16 pass (their
+// outputs fill the lower and the upper half of the sequence) and t + 512 i,
+// i = 0..7, of the radix-4 pass.  Between passes the outputs go through the
+// LDS buffer buf one half at a time: the lower half is written, every thread
+// reads the next pass's inputs that lie there, then the same for the upper
+// half.  input(p) gives the sequence at position p; on return y[i][q] holds
+// the DFT at t + 512 i + 4096 q.  v[b][r]: the sequence at t + 512 b + 1024
+// r (overwritten).  t1, t2: the twiddle tables in LDS, loaded and
+// synchronised by the caller.
+__device__ __forceinline__ void fft16k(float2* __restrict__ buf, const float2* __restrict__ t1,
+                                       const float2* __restrict__ t2, float2 (&v)[2][16], float2 (&y)[8][4]) {
+    static_assert(kFftN == 16 * 16 * 16 * 4 && kFftN / 32 == kFftThreads, "pass plan of the 16384-point FFT");
+    const int t = threadIdx.x;
+#pragma unroll
     for (int shift = 0; shift < 12; shift += 4) {
         const int Ns = 1 << shift;
-        const int k = tid & (Ns - 1);
-        float2 v[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = a[pidx(tid + r * (kFftN / 16))];
-        if (shift > 0) {
-            const int step = k << (10 - shift);   // k N / (16 Ns)
-            float2 w[16];
-            w[1] = twiddle(t1, t2, step);
-            w[4] = twiddle(t1, t2, 4 * step);
-            w[2] = cmul(w[1], w[1]);
-            w[3] = cmul(w[1], w[2]);
-            w[5] = cmul(w[4], w[1]);
-            w[6] = cmul(w[4], w[2]);
-            w[7] = cmul(w[4], w[3]);
-            w[8] = cmul(w[4], w[4]);
-            w[9] = cmul(w[8], w[1]);
-            w[10] = cmul(w[8], w[2]);
-            w[11] = cmul(w[8], w[3]);
-            w[12] = cmul(w[8], w[4]);
-            w[13] = cmul(w[12], w[1]);
-            w[14] = cmul(w[12], w[2]);
-            w[15] = cmul(w[12], w[3]);
-#pragma unroll
-            for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+        for (int b = 0; b < 2; ++b) {
+            if (shift > 0) twiddle16(t1, t2, ((t + 512 * b) & (Ns - 1)) << (10 - shift), v[b]);
+            dft16(v[b]);
         }
-        dft16(v);
-        __syncthreads();
-        const int base = ((tid >> shift) << (shift + 4)) + k;
+        // butterfly b's outputs lie in half b; the next pass's inputs are
+        // (radix 16) positions t + 512 b + 1024 r, in half r / 8, or
+        // (radix 4) positions t + 512 i + 4096 r, in half r / 2
+        float2 u[32];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) a[pidx(base + q * Ns)] = v[q];
-        __syncthreads();
-    }
-    {   // radix 4, Ns = 4096: butterflies j = tid + 1024 q
-        constexpr int Q = kFftN / 4 / kFftThreads, shift = 12, Ns = 1 << shift;
-        float2 v[Q][4];
+        for (int half = 0; half < 2; ++half) {
+            const int j = t + 512 * half;
+            const int base = ((j >> shift) << (shift + 4)) + (j & (Ns - 1)) - kHalfN * half;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int j = tid + q * kFftThreads;
-            const int k = j & (Ns - 1);   // step = k N / (4 Ns) = k
+            for (int q = 0; q < 16; ++q) buf[pidx(base + q * Ns)] = v[half][q];
+            __syncthreads();
+            if (shift < 8) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[q][r] = a[pidx(j + r * (kFftN / 4))];
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 1; r < 4; ++r) v[q][r] = cmul(v[q][r], twiddle(t1, t2, r * k));
+                    for (int r = 8 * half; r < 8 * half + 8; ++r)
+                        u[16 * b + r] = buf[pidx(t + 512 * b + 1024 * r - kHalfN * half)];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int r = 2 * half; r < 2 * half + 2; ++r)
+                        u[4 * i + r] = buf[pidx(t + 512 * i + 4096 * r - kHalfN * half)];
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        if (shift < 8) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int j = tid + q * kFftThreads;
-            const int base = ((j >> shift) << (shift + 2)) + (j & (Ns - 1));
-            dft4(v[q][0], v[q][1], v[q][2], v[q][3]);
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[pidx(base + r * Ns)] = v[q][r];
+                for (int r = 0; r < 16; ++r) v[b][r] = u[16 * b + r];
+        } else {
+            // radix 4, Ns = 4096: butterfly j = t + 512 i < 4096, so k = j
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int j = t + 512 * i;
+                const float2 w1 = twiddle(t1, t2, j), w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+                y[i][0] = u[4 * i];
+                y[i][1] = cmul(u[4 * i + 1], w1);
+                y[i][2] = cmul(u[4 * i + 2], w2);
+                y[i][3] = cmul(u[4 * i + 3], w3);
+                dft4(y[i][0], y[i][1], y[i][2], y[i][3]);
+            }
         }
-        __syncthreads();
     }
 }
 
-// The twiddle tables into LDS (after the sequence).
-__device__ __forceinline__ void load_twiddles(float2* a, const float2* __restrict__ tw) {
-    float2* t1 = a + kPadded;
+// The twiddle tables into LDS (after the exchange buffer); the caller
+// synchronises before the first pass that reads them.
+__device__ __forceinline__ void load_twiddles(float2* buf, const float2* __restrict__ tw) {
+    float2* t1 = buf + kHalfPadded;
     for (int i = threadIdx.x; i < kT1 + kT2; i += kFftThreads) t1[i] = i < kT1 ? tw[64 * i] : tw[i - kT1];
 }
 
@@ -191,20 +220,26 @@ __device__ __forceinline__ int room_of_chan(const void* desc, int c) {
     return lo;
 }
 
+// Bin k of the real spectrum from zk = Z[k] and zc = conj(Z[N - k]) (Z[N] =
+// Z[0]): X[k] = (zk + zc) / 2 - (i / 2) e^(-2 pi i k / L) (zk - zc).
+__device__ __forceinline__ float2 real_bin(float2 zk, float2 zc, float2 rk) {
+    const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+    const float2 d = cmul(rk, make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y)));
+    return make_float2(e.x + d.y, e.y - d.x);   // e - i d
+}
+
 // Spectrum of a real segment of kFftL samples: packed as z[n] = s[2n] + i
-// s[2n+1], transformed, then X[k] = (Z[k] + Z*[N-k]) / 2 - (i / 2) e^(-2 pi i k
-// / L) (Z[k] - Z*[N-k]) for k = 0..N.  Jobs: one per RIR channel (the RIR at
-// the start of the segment, zeros after it), then one per (source, block j)
-// (signal samples j B - (Tm - 1) + n, zeros outside [0, N_s)).
-__global__ void __launch_bounds__(kFftThreads) spectrum_kernel(const void* __restrict__ desc,
-                                                               const float* __restrict__ rir,
-                                                               const float* __restrict__ sig,
-                                                               const float2* __restrict__ tw,
-                                                               const float2* __restrict__ rt,
-                                                               float2* __restrict__ hspec,
-                                                               float2* __restrict__ xspec, int n_chan, int n_blk,
-                                                               int adv, int tm, int n_samples) {
-    extern __shared__ float2 a[];
+// s[2n+1] and transformed; bins k and N - k both need Z[k] and Z[N - k], so
+// the transform goes through the LDS buffer once more, half by half, and
+// thread t forms bins k and N - k for k = t + 512 i, i = 0..15 (thread 0 also
+// bin N/2).  Jobs: one per RIR channel (the RIR at the start of the segment,
+// zeros after it), then one per (source, block j) (signal samples j B - (Tm -
+// 1) + n, zeros outside [0, N_s)).
+__global__ void __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4)))
+spectrum_kernel(const void* __restrict__ desc, const float* __restrict__ rir, const float* __restrict__ sig,
+                const float2* __restrict__ tw, const float2* __restrict__ rt, float2* __restrict__ hspec,
+                float2* __restrict__ xspec, int n_chan, int n_blk, int adv, int tm, int n_samples) {
+    extern __shared__ float2 buf[];
     const int job = blockIdx.x;
     const float* seg;
     int64_t first;          // sample index of segment position 0
@@ -224,79 +259,145 @@ __global__ void __launch_bounds__(kFftThreads) spectrum_kernel(const void* __res
         len = n_samples;
         dst = xspec + static_cast<int64_t>(q) * kBins;
     }
-    constexpr int G = 4;   // iterations whose loads are in flight together
-    for (int n0 = threadIdx.x; n0 < kFftN; n0 += G * kFftThreads) {
-        float2 v[G];
+    load_twiddles(buf, tw);
+    const int t = threadIdx.x;
+    float2 v[2][16];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t i0 = first + 2 * (n0 + g * kFftThreads), i1 = i0 + 1;
-            v[g] = make_float2(i0 >= 0 && i0 < len ? seg[i0] : 0.0f, i1 >= 0 && i1 < len ? seg[i1] : 0.0f);
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i0 = first + 2 * (t + 512 * b + 1024 * r), i1 = i0 + 1;
+            v[b][r] = make_float2(i0 >= 0 && i0 < len ? seg[i0] : 0.0f, i1 >= 0 && i1 < len ? seg[i1] : 0.0f);
         }
-#pragma unroll
-        for (int g = 0; g < G; ++g) a[pidx(n0 + g * kFftThreads)] = v[g];
-    }
-    load_twiddles(a, tw);
     __syncthreads();
-    fft_lds(a, a + kPadded, a + kPadded + kT1);
-    for (int k = threadIdx.x; k < kBins; k += kFftThreads) {
-        const float2 zk = a[pidx(k & (kFftN - 1))], zc = conj2(a[pidx((kFftN - k) & (kFftN - 1))]);
-        const float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-        const float2 d = cmul(rt[k], make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y)));
-        dst[k] = make_float2(e.x + d.y, e.y - d.x);   // e - i d
+    const float2* t1 = buf + kHalfPadded;
+    float2 y[8][4];
+    fft16k(buf, t1, t1 + kT1, v, y);
+    float2 zk[16], zm[16], zmid = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {   // y[i][q] is Z at t + 512 i + 4096 q, in half q / 2
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int q = 2 * half; q < 2 * half + 2; ++q) buf[pidx(t + 512 * i + 4096 * q - kHalfN * half)] = y[i][q];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int k = t + 512 * i;
+            if (half == 0) zk[i] = buf[pidx(k)];
+            else zm[i] = buf[pidx(k == 0 ? 0 : kFftN - k - kHalfN)];   // Z[N - k] (k = 0: replaced below)
+        }
+        if (half == 1) zmid = buf[pidx(0)];   // Z[N/2]
+        __syncthreads();
     }
+    zm[0] = t == 0 ? zk[0] : zm[0];   // k = 0 pairs with Z[N] = Z[0]
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int k = t + 512 * i;
+        dst[k] = real_bin(zk[i], conj2(zm[i]), rt[k]);
+        dst[kFftN - k] = real_bin(zm[i], conj2(zk[i]), rt[kFftN - k]);
+    }
+    if (t == 0) dst[kHalfN] = real_bin(zmid, conj2(zmid), rt[kHalfN]);
 }
 
 // One output block of one channel: P = X H, then the inverse real FFT by the
 // forward one: Z[k] = E[k] + i O[k], E = (P[k] + P*[N-k]) / 2, O = (P[k] -
 // P*[N-k]) e^(2 pi i k / L) / 2, z = conj(DFT(conj(Z))) / N, samples 2n and
 // 2n+1 = Re, Im z[n].  Samples Tm - 1 .. L - 1 of the block are the outputs
-// j B .. j B + B - 1 (overlap-save).
-__global__ void __launch_bounds__(kFftThreads) conv_block_kernel(const void* __restrict__ desc,
-                                                                 const float2* __restrict__ tw,
-                                                                 const float2* __restrict__ rt,
-                                                                 const float2* __restrict__ hspec,
-                                                                 const float2* __restrict__ xspec,
-                                                                 float* __restrict__ images, int n_blk, int adv,
-                                                                 int tm, int n_samples) {
-    extern __shared__ float2 a[];
+// j B .. j B + B - 1 (overlap-save).  Each thread forms P at its own input
+// positions k and takes P[N - k] from the thread that formed it, through the
+// LDS buffer half by half (k = 0 pairs with the Nyquist bin P[N], k = N/2
+// with itself); e^(2 pi i k / L) comes from the LDS twiddle tables.
+__global__ void __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4)))
+conv_block_kernel(const void* __restrict__ desc, const float2* __restrict__ tw, const float2* __restrict__ hspec,
+                  const float2* __restrict__ xspec, float* __restrict__ images, int n_blk, int adv, int tm,
+                  int n_samples) {
+    extern __shared__ float2 buf[];
     const int c = blockIdx.x / n_blk, j = blockIdx.x % n_blk;
     const int b = room_of_chan(desc, c);
     const RoomDesc& R = rooms(desc)[b];
     const int s = R.src0 + (c - R.chan0) / R.n_mic;
     const float2* H = hspec + static_cast<int64_t>(c) * kBins;
     const float2* X = xspec + (static_cast<int64_t>(s) * n_blk + j) * kBins;
-    constexpr int G = 4;   // iterations whose loads are in flight together
-    for (int k0 = threadIdx.x; k0 < kFftN; k0 += G * kFftThreads) {
-        float2 xa[G], ha[G], xb[G], hb[G], w[G];
+    load_twiddles(buf, tw);
+    const int t = threadIdx.x;
+    // P = X H at the thread's positions k = t + 512 b + 1024 r.  Z[k] needs
+    // P[k] and P[N - k]; positions r < 8 lie in the lower half of the
+    // sequence, their partners in the upper one, and the reverse.  The lower
+    // half's products go straight to the LDS buffer (so that not all of the
+    // loads are held in registers at once), the upper half's stay in
+    // registers; P[N] (the Nyquist bin, partner of k = 0) on thread 0.
+#pragma unroll 2
+    for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int k = k0 + g * kFftThreads;
-            xa[g] = X[k];
-            ha[g] = H[k];
-            xb[g] = X[kFftN - k];
-            hb[g] = H[kFftN - k];
-            w[g] = rt[k];
+        for (int b = 0; b < 2; ++b) {
+            const int k = t + 512 * b + 1024 * r;
+            buf[pidx(k)] = cmul(X[k], H[k]);
         }
+    float2 v[2][16], pn = make_float2(0.0f, 0.0f);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const float2 p = cmul(xa[g], ha[g]), pc = conj2(cmul(xb[g], hb[g]));
-            const float2 e = make_float2(0.5f * (p.x + pc.x), 0.5f * (p.y + pc.y));
-            const float2 o = cmul(conj2(w[g]), make_float2(0.5f * (p.x - pc.x), 0.5f * (p.y - pc.y)));
-            a[pidx(k0 + g * kFftThreads)] = make_float2(e.x - o.y, -(e.y + o.x));   // conj(e + i o)
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 8; r < 16; ++r) {
+            const int k = t + 512 * b + 1024 * r;
+            v[b][r] = cmul(X[k], H[k]);
         }
-    }
-    load_twiddles(a, tw);
+    if (t == 0) pn = cmul(X[kFftN], H[kFftN]);
+    const float2* t1 = buf + kHalfPadded;
+    auto zform = [&](float2 pk, float2 pnk, int k) {   // Z[k] from P[k] and P[N - k]
+        const float2 wl = make_float2(0.99999998161642933f, -1.9174759731070331e-4f);   // e^(-pi i / N)
+        const float2 tk = twiddle(t1, t1 + kT1, k >> 1);
+        const float2 rk = (k & 1) ? cmul(tk, wl) : tk;   // e^(-2 pi i k / L)
+        const float2 pc = conj2(pnk);
+        const float2 e = make_float2(0.5f * (pk.x + pc.x), 0.5f * (pk.y + pc.y));
+        const float2 o = cmul(conj2(rk), make_float2(0.5f * (pk.x - pc.x), 0.5f * (pk.y - pc.y)));
+        return make_float2(e.x - o.y, -(e.y + o.x));   // conj(e + i o)
+    };
     __syncthreads();
-    fft_lds(a, a + kPadded, a + kPadded + kT1);
-    constexpr float inv_n = 1.0f / kFftN;
-    float* y = images + static_cast<int64_t>(c) * n_samples;
-    const int64_t o0 = static_cast<int64_t>(j) * adv - (tm - 1);   // output index of segment sample 0
-    for (int n = threadIdx.x; n < kFftN; n += kFftThreads) {
-        const float2 w = a[pidx(n)];
-        const int64_t i0 = o0 + 2 * n, i1 = i0 + 1;
-        if (2 * n >= tm - 1 && i0 < n_samples) y[i0] = w.x * inv_n;
-        if (2 * n + 1 >= tm - 1 && i1 < n_samples) y[i1] = -w.y * inv_n;
+    float2 zu[2][8];   // Z at the upper positions
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[b][r] = buf[pidx(t + 512 * b + 1024 * r)];   // own lower products back
+#pragma unroll
+        for (int r = 8; r < 16; ++r) {   // partner N - k in the lower half, except k = N/2 (itself)
+            const int k = t + 512 * b + 1024 * r;
+            const float2 q = buf[pidx(k == kHalfN ? 0 : kFftN - k)];
+            zu[b][r - 8] = zform(v[b][r], k == kHalfN ? v[b][r] : q, k);
+        }
     }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 8; r < 16; ++r) buf[pidx(t + 512 * b + 1024 * r - kHalfN)] = v[b][r];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {   // partner N - k in the upper half, except k = 0 (the Nyquist bin)
+            const int k = t + 512 * b + 1024 * r;
+            const float2 q = buf[pidx(k == 0 ? 0 : kHalfN - k)];
+            v[b][r] = zform(v[b][r], k == 0 ? pn : q, k);
+        }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 8; r < 16; ++r) v[b][r] = zu[b][r - 8];
+    float2 y[8][4];
+    fft16k(buf, t1, t1 + kT1, v, y);
+    constexpr float inv_n = 1.0f / kFftN;
+    float* out = images + static_cast<int64_t>(c) * n_samples;
+    const int o0 = j * adv - (tm - 1);   // output index of segment sample 0 (n_samples < 2^31)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int n2 = 2 * (static_cast<int>(threadIdx.x) + 512 * i + 4096 * q);
+            if (n2 >= tm - 1 && o0 + n2 < n_samples) out[o0 + n2] = y[i][q].x * inv_n;
+            if (n2 + 1 >= tm - 1 && o0 + n2 + 1 < n_samples) out[o0 + n2 + 1] = -y[i][q].y * inv_n;
+        }
 }
 
 // Per room: E1, E2, E12 = sum y0 y1 and En over all microphones and samples,
@@ -465,7 +566,7 @@ extern "C" int framrir_spatialize(const framrir_plan* plan, const void* desc_dev
     hipLaunchKernelGGL(spectrum_kernel, dim3(n_chan + n_src * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev,
                        rir_dev, sig_dev, tw, rt, hspec, xspec, n_chan, L.n_blk, L.adv, L.tm, n_samples);
     if (int rc = check("spectrum_kernel")) return rc;
-    hipLaunchKernelGGL(conv_block_kernel, dim3(n_chan * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev, tw, rt,
+    hipLaunchKernelGGL(conv_block_kernel, dim3(n_chan * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev, tw,
                        hspec, xspec, images_dev, L.n_blk, L.adv, L.tm, n_samples);
     if (int rc = check("conv_block_kernel")) return rc;
     double* partials = reinterpret_cast<double*>(w + L.e_off);
