@@ -385,7 +385,7 @@ def main():
 def spatial_hbm_bytes(plan, n):
     """Algorithmic HBM bytes of one framrir_spatialize call: the RIR spectra
     (written once, read by each of the channel's blocks), the signal-block
-    spectra (written once, read by each microphone's channel), the RIRs and
+    spectra (written once, read by each microphone of the room), the RIRs and
     signals read, the images written, read for the energies, then read and
     written scaled, and the mixtures written."""
     import numpy as np
@@ -393,7 +393,7 @@ def spatial_hbm_bytes(plan, n):
     tm = int(np.max(plan.T))
     n_blk = -(-n // (32768 - tm + 1))
     n_chan, n_src, n_mic = plan.info.n_chan, plan.info.n_src, plan.info.n_mic
-    spectra = n_chan * bins * (1 + n_blk) + n_src * n_blk * bins * (1 + 4)
+    spectra = n_chan * bins * (1 + n_blk) + n_src * n_blk * bins + n_chan * n_blk * bins
     inputs = 4 * int(plan.info.out_floats) + 4 * n_src * n_blk * 32768
     images = 4 * 4 * n_chan * n
     return spectra + inputs + images + 4 * n_mic * n
