@@ -110,31 +110,62 @@ def workload(name):
     return W.config1(), "one room 6x5x3 m, T60 0.4 s, 16 kHz, 1 source, 2 mics"
 
 
+def room_slice(batch, b0, b1):
+    """Rooms b0 .. b1-1 of a batch, with their sources and microphones."""
+    import numpy as np
+    s0, s1 = (int(np.sum(batch["n_src"][:b])) for b in (b0, b1))
+    m0, m1 = (int(np.sum(batch["n_mic"][:b])) for b in (b0, b1))
+    sub = dict(batch)
+    for k in ("size", "rt60", "fs", "c", "r_override", "seed", "n_src", "n_mic"):
+        sub[k] = batch[k][b0:b1]
+    sub["src"] = batch["src"][s0:s1]
+    sub["mic"] = batch["mic"][m0:m1]
+    return sub
+
+
+def _oracle_rooms(sub):
+    """Worker of cpu_baseline_parallel: the oracle on a few rooms, one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import framrir as F
+    with threadpool_limits(limits=1):
+        F.simulate(sub)
+    return 0
+
+
 def cpu_baseline(batch, n_rooms):
     """The FP64 oracle as it stands, on the first n_rooms rooms, one thread."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:      # pragma: no cover
-        threadpool_limits = None
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import framrir as F
-    sub = {k: v for k, v in batch.items()}
     nb = min(n_rooms, len(batch["rt60"]))
     ns = int(np.sum(batch["n_src"][:nb]))
-    nm = int(np.sum(batch["n_mic"][:nb]))
-    for k in ("size", "rt60", "fs", "c", "r_override", "seed", "n_src", "n_mic"):
-        sub[k] = batch[k][:nb]
-    sub["src"] = batch["src"][:ns]
-    sub["mic"] = batch["mic"][:nm]
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    t0 = time.perf_counter()
-    F.simulate(sub)
-    dt = time.perf_counter() - t0
-    if ctx is not None:
-        ctx.unregister() if hasattr(ctx, "unregister") else None
+    sub = room_slice(batch, 0, nb)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        F.simulate(sub)
+        dt = time.perf_counter() - t0
     return dict(value=ns / dt, unit="RIR/s", cores=1, kind="oracle",
                 sample=f"first {nb} rooms ({ns} multi-channel RIRs) of the same workload, "
                        f"FP64 numpy oracle, {dt:.2f} s on 1 thread")
+
+
+def cpu_baseline_parallel(batch, n_rooms):
+    """The same oracle on the same rooms, one room per task over a pool of
+    worker processes (one per available host core, at most 16, each single
+    threaded).  Forked before the GPU is touched."""
+    import multiprocessing as mp
+    import numpy as np
+    nb = min(n_rooms, len(batch["rt60"]))
+    ns = int(np.sum(batch["n_src"][:nb]))
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    subs = [room_slice(batch, b, b + 1) for b in range(nb)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        pool.map(_oracle_rooms, subs, chunksize=1)
+        dt = time.perf_counter() - t0
+    return dict(value=ns / dt, unit="RIR/s", cores=workers, kind="oracle",
+                sample=f"first {nb} rooms ({ns} multi-channel RIRs) of the same workload, "
+                       f"FP64 numpy oracle, {dt:.2f} s on {workers} single-threaded processes")
 
 
 def main():
@@ -170,6 +201,9 @@ def main():
         return run_mixed(args, batch, desc, launch)
     if args.workload == "multirate":
         return run_multirate(args, batch, desc, launch)
+    # the oracle on all host cores first: its worker processes fork before
+    # anything here touches the GPU
+    cpu_par = cpu_baseline_parallel(batch, args.cpu_rooms) if args.cpu_rooms > 0 else None
     tuned = None
     if not args.tune and not launch:
         from paper_2304_08052_amd import autotune
@@ -229,7 +263,8 @@ def main():
     t_end.record(stream)
     torch.cuda.synchronize()
     eager_ms = t_start.elapsed_time(t_end) / args.steps
-    render_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    render_each = np.array([a.elapsed_time(b) for a, b in evs])
+    render_ms = float(np.mean(render_each))
 
     # ---- hipGraph-captured forward step (draw + render)
     graph_ms = None
@@ -365,10 +400,12 @@ def main():
             "tap_updates_per_launch": taps,
             "flops_per_tap": FLOPS_PER_TAP,
             "render_ms": render_ms,
+            "render_ms_p10_p50_p90": [float(np.percentile(render_each, q)) for q in (10, 50, 90)],
             "hbm_write_gbs": out_bytes / (render_ms * 1e-3) / 1e9,
             "hbm_frac": out_bytes / (render_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_par,
         "eager_ms_per_step": eager_ms,
         "graph_ms_per_step": graph_ms,
         "fwd_bwd_ms_per_step": fb_ms,
