@@ -35,6 +35,7 @@ FLOPS_PER_TAP = 11          # sub, rcp, 2 mul + FMA (window), FMA, mul, add
 
 KERNEL_SOURCES = ["kernels.hip", "framrir_internal.h", "tap_poly.h", "plan.cpp", "plan_internal.h"]
 HBM_PROFILE = os.path.join(HERE, "profiles", "render_kernel_batched256_hbm.md")
+VALU_PROFILE = os.path.join(HERE, "profiles", "render_kernel_batched256_valu.md")
 
 
 def kernel_sources_sha256():
@@ -46,13 +47,12 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload_name, launch):
-    """HBM bytes per render launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy kernel of known size),
-    or None when the kernel sources, the workload or the launch shape differ
-    from the ones the counters were taken on."""
+def profile_values(path, workload_name, launch):
+    """The key = value lines of a committed rocprofv3 counter summary, or None
+    when the kernel sources, the workload or the launch shape differ from the
+    ones the counters were taken on."""
     try:
-        with open(HBM_PROFILE) as f:
+        with open(path) as f:
             kv = dict(line.split(" = ", 1) for line in f.read().splitlines() if " = " in line)
     except OSError:
         return None
@@ -61,7 +61,21 @@ def measured_traffic(workload_name, launch):
     if (kv.get("workload") != workload_name or kv.get("launch") != shape
             or kv.get("source_sha256") != kernel_sources_sha256()):
         return None
-    return int(kv["traffic_bytes"])
+    return kv
+
+
+def measured_traffic(workload_name, launch):
+    """HBM bytes per render launch from the committed FETCH_SIZE and WRITE_SIZE
+    passes (scaled by a copy kernel of known size), or None (profile_values)."""
+    kv = profile_values(HBM_PROFILE, workload_name, launch)
+    return int(kv["traffic_bytes"]) if kv else None
+
+
+def measured_valu_insts(workload_name, launch):
+    """VALU and LDS wave instructions per render launch from the committed
+    SQ counter pass, or None (profile_values)."""
+    kv = profile_values(VALU_PROFILE, workload_name, launch)
+    return (int(kv["valu_wave_insts"]), int(kv["lds_wave_insts"])) if kv else None
 
 
 def parse_args():
@@ -356,6 +370,10 @@ def main():
     achieved = taps * FLOPS_PER_TAP / (render_ms * 1e-3) / 1e12
     cpu = cpu_baseline(batch, args.cpu_rooms) if args.cpu_rooms > 0 else None
     traffic = measured_traffic(args.workload, plan.launch)
+    insts = measured_valu_insts(args.workload, plan.launch)
+    # a wave64 VALU instruction holds a 16-lane SIMD for 4 clocks: 1,024 SIMDs
+    # at 2.4 GHz issue at most 614.4 G wave instructions per second
+    valu_issue = insts[0] / (render_ms * 1e-3) / (1024 * 2.4e9 / 4) if insts else None
     # algorithmic render bytes: every image row (32 B) read once per microphone
     # group of its source, every output sample (4 B) written once
     groups = np.repeat(-(-batch["n_mic"] // plan.launch["max_mic_group"]), batch["n_src"]).astype(np.int64)
@@ -401,6 +419,9 @@ def main():
             "flops_per_tap": FLOPS_PER_TAP,
             "render_ms": render_ms,
             "render_ms_p10_p50_p90": [float(np.percentile(render_each, q)) for q in (10, 50, 90)],
+            "valu_issue_frac_counters": valu_issue,
+            "valu_lds_wave_insts_counters": list(insts) if insts else None,
+            "counters_source": os.path.relpath(VALU_PROFILE, HERE) if insts else None,
             "hbm_write_gbs": out_bytes / (render_ms * 1e-3) / 1e9,
             "hbm_frac": out_bytes / (render_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
