@@ -36,15 +36,42 @@ FLOPS_PER_TAP = 11          # sub, rcp, 2 mul + FMA (window), FMA, mul, add
 KERNEL_SOURCES = ["kernels.hip", "framrir_internal.h", "tap_poly.h", "plan.cpp", "plan_internal.h"]
 HBM_PROFILE = os.path.join(HERE, "profiles", "render_kernel_batched256_hbm.md")
 VALU_PROFILE = os.path.join(HERE, "profiles", "render_kernel_batched256_valu.md")
+SPATIAL_SOURCES = ["spatial.hip", "framrir_internal.h", "plan_internal.h"]
+SPATIAL_HBM_PROFILE = os.path.join(HERE, "profiles", "spatial_batched256_hbm.md")
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(files=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (KERNEL_SOURCES if files is None else files):
         with open(os.path.join(HERE, "paper_2304_08052_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def copy_probe(mib):
+    """One elementwise kernel of known traffic (mib MiB read, mib MiB written)
+    for scaling the FETCH_SIZE / WRITE_SIZE counters of the same run."""
+    import torch
+    a = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+
+
+def measured_spatial_traffic():
+    """HBM bytes of one framrir_spatialize call on the training-mixture
+    workload from the committed counter passes, or None when the
+    spatialisation sources differ from the ones the counters were taken on."""
+    try:
+        with open(SPATIAL_HBM_PROFILE) as f:
+            kv = dict(line.split(" = ", 1) for line in f.read().splitlines() if " = " in line)
+    except OSError:
+        return None
+    if kv.get("workload") != "spatial" or kv.get("source_sha256") != kernel_sources_sha256(SPATIAL_SOURCES):
+        return None
+    return int(kv["traffic_bytes"])
 
 
 def profile_values(path, workload_name, launch):
@@ -242,12 +269,7 @@ def main():
     grad = torch.from_numpy(W.upstream_grad(info.out_floats)).cuda()
     stream = torch.cuda.current_stream()
     if args.copy_probe_mb > 0:   # known traffic: N MiB read + N MiB written (one elementwise kernel)
-        a = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        torch.neg(a, out=b)
-        torch.cuda.synchronize()
-        del a, b
+        copy_probe(args.copy_probe_mb)
 
     # forward step = framrir_forward split in its two launches: draws +
     # preparation, then the render kernel (timed on its own for the roofline)
@@ -481,6 +503,8 @@ def run_spatial(args, launch):
     gains = torch.empty(plan.info.n_src, dtype=torch.float32, device="cuda")
     ws_sp = torch.empty(plan.spatial_workspace_bytes(n), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    if args.copy_probe_mb > 0:
+        copy_probe(args.copy_probe_mb)
 
     def spatial():
         plan.spatialize(out, sig_d, sir_d, snr_d, images=images, mix=mix, gains=gains, ws=ws_sp)
@@ -532,7 +556,9 @@ def run_spatial(args, launch):
                    "rooms": 256, "samples": n, "launch": plan.launch},
         "roofline": {"bound": "hbm", "kernel": "framrir_spatialize (spectra, products + inverse FFTs, energies, "
                                               "mixing)", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": hbm,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_spatial_traffic(),
+                     "traffic_source": os.path.relpath(SPATIAL_HBM_PROFILE, HERE) if measured_spatial_traffic()
+                     else None, "algorithmic_bytes": hbm,
                      "spatial_ms": spatial_ms},
         "eager_ms_per_step": eager_ms, "graph_ms_per_step": graph_ms,
         "cpu_baseline": None,
