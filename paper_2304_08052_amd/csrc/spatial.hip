@@ -321,70 +321,68 @@ conv_block_kernel(const void* __restrict__ desc, const float2* __restrict__ tw, 
     const float2* X = xspec + (static_cast<int64_t>(s) * n_blk + j) * kBins;
     load_twiddles(buf, tw);
     const int t = threadIdx.x;
-    // P = X H at the thread's positions k = t + 512 b + 1024 r.  Z[k] needs
-    // P[k] and P[N - k]; positions r < 8 lie in the lower half of the
-    // sequence, their partners in the upper one, and the reverse.  The lower
-    // half's products go straight to the LDS buffer (so that not all of the
-    // loads are held in registers at once), the upper half's stay in
-    // registers; P[N] (the Nyquist bin, partner of k = 0) on thread 0.
-#pragma unroll 2
-    for (int r = 0; r < 8; ++r)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int k = t + 512 * b + 1024 * r;
-            buf[pidx(k)] = cmul(X[k], H[k]);
-        }
-    float2 v[2][16], pn = make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 8; r < 16; ++r) {
-            const int k = t + 512 * b + 1024 * r;
-            v[b][r] = cmul(X[k], H[k]);
-        }
-    if (t == 0) pn = cmul(X[kFftN], H[kFftN]);
+    // Z[k] needs P[k] = X[k] H[k] and P[N - k].  The thread's positions are
+    // k = t + 512 b + 1024 r; for t >= 1 the partner of (t, b = 0, r) is (512
+    // - t, b = 1, 15 - r), so thread t forms both Z of each of its b = 0
+    // pairs: the b = 1 products go to the LDS buffer (slot r 512 + t), the
+    // thread reads its partner's product there and puts the partner's Z in
+    // its place.  Thread 0's pairs are among its own positions (0 with the
+    // Nyquist bin P[N], N/2 with itself).  r_(N - k) = -conj(r_k).
     const float2* t1 = buf + kHalfPadded;
-    auto zform = [&](float2 pk, float2 pnk, int k) {   // Z[k] from P[k] and P[N - k]
+    auto rt_of = [&](int k) {   // e^(-2 pi i k / L)
         const float2 wl = make_float2(0.99999998161642933f, -1.9174759731070331e-4f);   // e^(-pi i / N)
         const float2 tk = twiddle(t1, t1 + kT1, k >> 1);
-        const float2 rk = (k & 1) ? cmul(tk, wl) : tk;   // e^(-2 pi i k / L)
+        return (k & 1) ? cmul(tk, wl) : tk;
+    };
+    auto zform = [](float2 pk, float2 pnk, float2 rk) {   // Z[k] from P[k], P[N - k], r_k
         const float2 pc = conj2(pnk);
         const float2 e = make_float2(0.5f * (pk.x + pc.x), 0.5f * (pk.y + pc.y));
         const float2 o = cmul(conj2(rk), make_float2(0.5f * (pk.x - pc.x), 0.5f * (pk.y - pc.y)));
         return make_float2(e.x - o.y, -(e.y + o.x));   // conj(e + i o)
     };
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int k = t + 512 + 1024 * r;
+        buf[r * kFftThreads + t] = cmul(X[k], H[k]);
+    }
+    float2 v[2][16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int k = t + 1024 * r;
+        v[0][r] = cmul(X[k], H[k]);
+    }
     __syncthreads();
-    float2 zu[2][8];   // Z at the upper positions
+    if (t != 0) {
+        const int tp = kFftThreads - t;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-#pragma unroll
-        for (int r = 0; r < 8; ++r) v[b][r] = buf[pidx(t + 512 * b + 1024 * r)];   // own lower products back
-#pragma unroll
-        for (int r = 8; r < 16; ++r) {   // partner N - k in the lower half, except k = N/2 (itself)
-            const int k = t + 512 * b + 1024 * r;
-            const float2 q = buf[pidx(k == kHalfN ? 0 : kFftN - k)];
-            zu[b][r - 8] = zform(v[b][r], k == kHalfN ? v[b][r] : q, k);
+        for (int r = 0; r < 16; ++r) {
+            float2* slot = buf + (15 - r) * kFftThreads + tp;
+            const float2 p = *slot;
+            const float2 rk = rt_of(t + 1024 * r);
+            *slot = zform(p, v[0][r], make_float2(-rk.x, rk.y));
+            v[0][r] = zform(v[0][r], p, rk);
         }
+    } else {
+        const float2 pn = cmul(X[kFftN], H[kFftN]);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {   // b = 1: (512 + 1024 r) with (512 + 1024 (15 - r))
+            const float2 a1 = buf[r * kFftThreads], b1 = buf[(15 - r) * kFftThreads];
+            buf[r * kFftThreads] = zform(a1, b1, rt_of(512 + 1024 * r));
+            buf[(15 - r) * kFftThreads] = zform(b1, a1, rt_of(512 + 1024 * (15 - r)));
+        }
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {   // b = 0: 1024 r with 1024 (16 - r)
+            const float2 a0 = v[0][r], b0 = v[0][16 - r];
+            v[0][r] = zform(a0, b0, rt_of(1024 * r));
+            v[0][16 - r] = zform(b0, a0, rt_of(1024 * (16 - r)));
+        }
+        v[0][0] = zform(v[0][0], pn, rt_of(0));
+        v[0][8] = zform(v[0][8], v[0][8], rt_of(kHalfN));
     }
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 8; r < 16; ++r) buf[pidx(t + 512 * b + 1024 * r - kHalfN)] = v[b][r];
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {   // partner N - k in the upper half, except k = 0 (the Nyquist bin)
-            const int k = t + 512 * b + 1024 * r;
-            const float2 q = buf[pidx(k == 0 ? 0 : kHalfN - k)];
-            v[b][r] = zform(v[b][r], k == 0 ? pn : q, k);
-        }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 8; r < 16; ++r) v[b][r] = zu[b][r - 8];
+    for (int r = 0; r < 16; ++r) v[1][r] = buf[r * kFftThreads + t];
+    __syncthreads();   // the transform reuses the buffer
     float2 y[8][4];
     fft16k(buf, t1, t1 + kT1, v, y);
     constexpr float inv_n = 1.0f / kFftN;
