@@ -229,12 +229,11 @@ __device__ __forceinline__ float2 real_bin(float2 zk, float2 zc, float2 rk) {
 }
 
 // Spectrum of a real segment of kFftL samples: packed as z[n] = s[2n] + i
-// s[2n+1] and transformed; bins k and N - k both need Z[k] and Z[N - k], so
-// the transform goes through the LDS buffer once more, half by half, and
-// thread t forms bins k and N - k for k = t + 512 i, i = 0..15 (thread 0 also
-// bin N/2).  Jobs: one per RIR channel (the RIR at the start of the segment,
-// zeros after it), then one per (source, block j) (signal samples j B - (Tm -
-// 1) + n, zeros outside [0, N_s)).
+// s[2n+1] and transformed; bins k and N - k both need Z[k] and Z[N - k],
+// which thread pairs (t, 512 - t) exchange through the LDS buffer.  Jobs: one
+// per RIR channel (the RIR at the start of the segment, zeros after it), then
+// one per (source, block j) (signal samples j B - (Tm - 1) + n, zeros outside
+// [0, N_s)).
 __global__ void __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4)))
 spectrum_kernel(const void* __restrict__ desc, const float* __restrict__ rir, const float* __restrict__ sig,
                 const float2* __restrict__ tw, const float2* __restrict__ rt, float2* __restrict__ hspec,
@@ -273,31 +272,30 @@ spectrum_kernel(const void* __restrict__ desc, const float* __restrict__ rir, co
     const float2* t1 = buf + kHalfPadded;
     float2 y[8][4];
     fft16k(buf, t1, t1 + kT1, v, y);
-    float2 zk[16], zm[16], zmid = make_float2(0.0f, 0.0f);
+    // y[i][q] is Z at p = t + 512 i + 4096 q; for t >= 1 the partner N - p is
+    // (512 - t, 7 - i, 3 - q): the q >= 2 values go to the LDS buffer (slot
+    // (2 i + q - 2) 512 + t) and thread t forms bins p and N - p for its q < 2
+    // positions from its own value and its partner's.  Thread 0 does the
+    // same with partners among its own values, (N - p) mod N = (8 - i, 3 - q)
+    // or, for i = 0, (0, -q mod 4), which also gives bin N from p = 0; bin
+    // N/2 (its position (0, 2)) it forms alone.
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {   // y[i][q] is Z at t + 512 i + 4096 q, in half q / 2
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int q = 2; q < 4; ++q) buf[(2 * i + q - 2) * kFftThreads + t] = y[i][q];
+    __syncthreads();
+    const int tp = (kFftThreads - t) & (kFftThreads - 1);   // partner thread (thread 0: unused slot)
 #pragma unroll
-            for (int q = 2 * half; q < 2 * half + 2; ++q) buf[pidx(t + 512 * i + 4096 * q - kHalfN * half)] = y[i][q];
-        __syncthreads();
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int k = t + 512 * i;
-            if (half == 0) zk[i] = buf[pidx(k)];
-            else zm[i] = buf[pidx(k == 0 ? 0 : kFftN - k - kHalfN)];   // Z[N - k] (k = 0: replaced below)
+        for (int q = 0; q < 2; ++q) {
+            const int p = t + 512 * i + 4096 * q;
+            const float2 own = i == 0 ? y[0][(4 - q) & 3] : y[8 - i][3 - q];
+            const float2 zp = t == 0 ? own : buf[(2 * (7 - i) + 1 - q) * kFftThreads + tp];
+            dst[p] = real_bin(y[i][q], conj2(zp), rt[p]);
+            dst[kFftN - p] = real_bin(zp, conj2(y[i][q]), rt[kFftN - p]);
         }
-        if (half == 1) zmid = buf[pidx(0)];   // Z[N/2]
-        __syncthreads();
-    }
-    zm[0] = t == 0 ? zk[0] : zm[0];   // k = 0 pairs with Z[N] = Z[0]
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int k = t + 512 * i;
-        dst[k] = real_bin(zk[i], conj2(zm[i]), rt[k]);
-        dst[kFftN - k] = real_bin(zm[i], conj2(zk[i]), rt[kFftN - k]);
-    }
-    if (t == 0) dst[kHalfN] = real_bin(zmid, conj2(zmid), rt[kHalfN]);
+    if (t == 0) dst[kHalfN] = real_bin(y[0][2], conj2(y[0][2]), rt[kHalfN]);
 }
 
 // One output block of one channel: P = X H, then the inverse real FFT by the
