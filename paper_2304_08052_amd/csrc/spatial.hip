@@ -400,7 +400,7 @@ conv_block_kernel(const void* __restrict__ desc, const float2* __restrict__ tw, 
 // split over kEnergyParts workgroups (blocks (part, room)), each thread
 // summing a fixed set of samples in FP64, then a fixed reduction tree; one
 // set of partial sums per workgroup.
-constexpr int kEnergyParts = 16;
+constexpr int kEnergyParts = 64;
 constexpr int kEnergyThreads = 256;
 __global__ void __launch_bounds__(kEnergyThreads) spatial_energy_kernel(const void* __restrict__ desc,
                                                                         const float* __restrict__ images,
@@ -436,18 +436,22 @@ __global__ void __launch_bounds__(kEnergyThreads) spatial_energy_kernel(const vo
     if (tid < 4) partials[(static_cast<int64_t>(b) * kEnergyParts + part) * 4 + tid] = red[tid][0];
 }
 
-// Per room: the partial energies summed in part order, then the gains
+// Per room (one wave): the partial energies summed by a fixed tree (lane l
+// takes parts l, l + 64, ..., then a butterfly over the lanes), then the gains
 // (1, g2, gn) of the room's SIR and SNR (a silent source gets gain 0).
-__global__ void spatial_gain_kernel(const void* __restrict__ desc, const double* __restrict__ partials,
-                                    const float* __restrict__ sir_db, const float* __restrict__ snr_db,
-                                    float* __restrict__ gains, int n_rooms) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_rooms) return;
+__global__ void __launch_bounds__(64) spatial_gain_kernel(const void* __restrict__ desc,
+                                                          const double* __restrict__ partials,
+                                                          const float* __restrict__ sir_db,
+                                                          const float* __restrict__ snr_db, float* __restrict__ gains) {
+    const int b = blockIdx.x, lane = threadIdx.x;
     const RoomDesc& R = rooms(desc)[b];
     double e[4] = {0.0, 0.0, 0.0, 0.0};
     const double* pb = partials + static_cast<int64_t>(b) * kEnergyParts * 4;
-    for (int p = 0; p < kEnergyParts; ++p)
+    for (int p = lane; p < kEnergyParts; p += 64)
         for (int q = 0; q < 4; ++q) e[q] += pb[4 * p + q];
+    for (int off = 32; off > 0; off >>= 1)
+        for (int q = 0; q < 4; ++q) e[q] += __shfl_xor(e[q], off);
+    if (lane != 0) return;
     const double e1 = e[0], e2 = e[1], e12 = e[2], en = e[3];
     const double g2 = e2 > 0.0 ? sqrt(e1 / (e2 * exp10(static_cast<double>(sir_db[b]) / 10.0))) : 0.0;
     const double esp = e1 + 2.0 * g2 * e12 + g2 * g2 * e2;
@@ -569,8 +573,8 @@ extern "C" int framrir_spatialize(const framrir_plan* plan, const void* desc_dev
     hipLaunchKernelGGL(spatial_energy_kernel, dim3(kEnergyParts, n_rooms), dim3(kEnergyThreads), 0, st, desc_dev,
                        images_dev, partials, n_samples);
     if (int rc = check("spatial_energy_kernel")) return rc;
-    hipLaunchKernelGGL(spatial_gain_kernel, dim3((n_rooms + 63) / 64), dim3(64), 0, st, desc_dev, partials, sir_db_dev,
-                       snr_db_dev, gains_dev, n_rooms);
+    hipLaunchKernelGGL(spatial_gain_kernel, dim3(n_rooms), dim3(64), 0, st, desc_dev, partials, sir_db_dev,
+                       snr_db_dev, gains_dev);
     if (int rc = check("spatial_gain_kernel")) return rc;
     int max_per = 0;
     for (const RoomDesc& R : plan->rooms) max_per = std::max(max_per, R.n_mic);
