@@ -1461,7 +1461,8 @@ __global__ void __launch_bounds__(kDecThreads) decimate_kernel(const void* __res
                                                                const double* __restrict__ basis,
                                                                const float* __restrict__ dec_taps,
                                                                float* __restrict__ out) {
-    constexpr int NR = kDecPerThread, UNR = 8;
+    constexpr int NR = kDecPerThread, UNR = 4, kQ = kHpChunk / kDecThreads;
+    static_assert(kHpChunk == 256 && kQ * kDecThreads == kHpChunk, "staging by chunks of 256");
     extern __shared__ float span[];
     const DescHeader* H = hdr(desc);
     const int tid = threadIdx.x;
@@ -1473,6 +1474,12 @@ __global__ void __launch_bounds__(kDecThreads) decimate_kernel(const void* __res
         const float* taps = dec_taps + static_cast<int64_t>(b) * kDecTapStride;
         const double* ha = basis + static_cast<int64_t>(b) * kHpBasisStride;
         const double* hb = ha + kHpChunk;
+        double hav[kQ], hbv[kQ];   // the thread's basis values (offsets tid + 64 q)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            hav[q] = ha[tid + kDecThreads * q];
+            hbv[q] = hb[tid + kDecThreads * q];
+        }
         const int n_tiles = (R->T_out + kDecOut - 1) / kDecOut;
         for (int local = blockIdx.z; local < R->n_src * R->n_mic; local += gridDim.z) {
             const float* xc = y0 + R->out_off + static_cast<int64_t>(local) * R->T;
@@ -1482,22 +1489,39 @@ __global__ void __launch_bounds__(kDecThreads) decimate_kernel(const void* __res
                 const int n0 = tile * kDecOut;
                 const int64_t jb = static_cast<int64_t>(n0) * rl - half;   // input index of span[0]
                 const int span_len = (kDecOut - 1) * rl + 2 * half + 1;
-                for (int i0 = tid; i0 < span_len; i0 += UNR * kDecThreads) {
-                    double v[UNR];
+                // staged by high-pass chunks: thread tid takes offsets o = tid +
+                // 64 q of every chunk k the span touches, so its basis values
+                // are loaded once and the chunk's carried state is uniform;
+                // UNR chunks' loads in flight together
+                const int64_t k_first = jb >> 8, k_last = (jb + span_len - 1) >> 8;   // kHpChunk = 256
+                for (int64_t k0 = k_first; k0 <= k_last; k0 += UNR) {
+                    float xv[UNR][kQ];
 #pragma unroll
-                    for (int e = 0; e < UNR; ++e) {   // all loads first: one latency per UNR samples
-                        const int64_t j = jb + i0 + e * kDecThreads;
-                        const bool in = i0 + e * kDecThreads < span_len && j >= 0 && j < R->T;
-                        v[e] = 0.0;
-                        if (in) {
-                            const int k = static_cast<int>(j / kHpChunk), o = static_cast<int>(j % kHpChunk);
-                            v[e] = xc[j];
-                            if (k > 0) v[e] += ic[2 * k] * ha[o] + ic[2 * k + 1] * hb[o];
+                    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                        for (int q = 0; q < kQ; ++q) {
+                            const int64_t j = (k0 + u) * kHpChunk + tid + kDecThreads * q;
+                            xv[u][q] = (k0 + u <= k_last && j >= 0 && j < R->T) ? xc[j] : 0.0f;
+                        }
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) {
+                        const int64_t k = k0 + u;
+                        if (k > k_last) break;
+                        const bool carry = k > 0 && k * kHpChunk < R->T;
+                        const double c0 = carry ? ic[2 * k] : 0.0, c1 = carry ? ic[2 * k + 1] : 0.0;
+#pragma unroll
+                        for (int q = 0; q < kQ; ++q) {
+                            const int64_t j = k * kHpChunk + tid + kDecThreads * q;
+                            const int64_t i = j - jb;
+                            if (i < 0 || i >= span_len) continue;
+                            double v = 0.0;
+                            if (j >= 0 && j < R->T) {
+                                v = xv[u][q];
+                                if (carry) v += c0 * hav[q] + c1 * hbv[q];
+                            }
+                            span[i] = static_cast<float>(v);
                         }
                     }
-#pragma unroll
-                    for (int e = 0; e < UNR; ++e)
-                        if (i0 + e * kDecThreads < span_len) span[i0 + e * kDecThreads] = static_cast<float>(v[e]);
                 }
                 __syncthreads();
                 float acc[NR];
