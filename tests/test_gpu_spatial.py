@@ -65,6 +65,18 @@ def test_spatialize_matches_oracle(n):
     _check_rooms(plan, out, sig, sir, snr, images, mix, gains, range(3), n)
 
 
+def test_spatialize_longest_rir_odd_window():
+    """The longest RIR the library takes (T60 1.024 s at 16 kHz: 16,384
+    samples, so an overlap-save block advances by 16,385) over an odd window
+    of 17,001 samples: two blocks, the second one ragged."""
+    batch = W.spatial_batch(1, seed=8, rt60_range=(1.024, 1.024))
+    n = 17001
+    say(f"spatialize the longest RIR, n = {n}")
+    plan, out, sig, sir, snr, images, mix, gains = _run(batch, n, seed=3)
+    assert int(plan.T[0]) == 16384
+    _check_rooms(plan, out, sig, sir, snr, images, mix, gains, range(1), n)
+
+
 def test_spatialize_full_workload_sampled():
     """The benchmark's workload (256 rooms, 4 s at 16 kHz, T60 up to 0.7 s):
     sampled rooms against the oracle, every room's identities checked."""
