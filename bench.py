@@ -25,7 +25,7 @@ if HERE not in sys.path:
 METRIC = "multi-channel RIRs/sec at batch 256, 16 kHz; fwd+bwd/fwd ratio; VALU/HBM % peak"
 
 # MI355X peaks.  HBM3E: 8 TB/s.  FP32 vector: 157.3 TFLOP/s is the published
-# figure with packed FP32 instructions, which this build disables; the
+# figure with packed FP32 instructions, which this library never emits; the
 # reachable non-packed rate is 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz.
 HBM_PEAK_GBS = 8000.0
 FP32_NONPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.64
@@ -213,7 +213,7 @@ def main():
     args = parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the path shards by room with no "
-              f"exchange, and multi-GPU runs are not part of this build.", file=sys.stderr)
+              f"exchange, and no multi-GPU launcher is provided.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
