@@ -1092,6 +1092,15 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
         ItemCtx c;
         load_item(desc, item, mic, r_in, c);
         const int mg = c.w.n_mic;
+        // Row stride of the staged tile.  The lanes of one image (one per
+        // microphone, nearly equal delays) read their rows at the same offset;
+        // where the LDS leaves room, rows start about 32 / mg banks apart so
+        // that those lanes fall in different banks.
+        int stride = c.rowlen;
+        {
+            const int padded = c.rowlen + (((32 + mg / 2) / mg - c.rowlen) & (kLdsBanks - 1));
+            if (mg * padded <= lds_words) stride = padded;
+        }
         // dL/dh of the tile core; zero in the halo and beyond T, so that each
         // pair counts only the taps of this tile
         for (int m = 0; m < mg; ++m) {
@@ -1100,7 +1109,7 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
             for (int k = tid; k < c.rowlen; k += NT) {
                 const int n = c.w.t0 - kHalo + k;
                 const bool core = k >= kHalo && k < kHalo + c.w.len && n < c.T;
-                tile[m * c.rowlen + k] = core ? g[n] : 0.0f;
+                tile[m * stride + k] = core ? g[n] : 0.0f;
             }
         }
         // rows that can reach this tile: a contiguous range of the delay order
@@ -1120,7 +1129,7 @@ backward_kernel(const void* __restrict__ desc, const double* __restrict__ mic, c
         const int my_m = tid % mg, my_slot = tid / mg;
         const double* mq = mic + 3 * (c.mic0_glob + my_m);
         const double mx = mq[0], my = mq[1], mz = mq[2];
-        const float* row = tile + my_m * c.rowlen;
+        const float* row = tile + my_m * stride;
         const int shift = kHalo - kHalf - c.w.t0;
         const float fsc = static_cast<float>(c.fs_over_c);
         const float inv_r = static_cast<float>(1.0 / c.r);
