@@ -1330,22 +1330,42 @@ __global__ void __launch_bounds__(256) early_kernel(const void* __restrict__ des
 // recurrence.  Blocks: (chunks / 64, rooms, channels of the room).
 
 // Coalesced move of one batch (samples off .. off + kHpBatch of 64 chunks)
-// between global memory g (the channel's first sample) and buf[chunk][i].
+// between global memory g (the channel's first sample) and buf[chunk][i]:
+// instruction it moves sample i = lane mod kHpBatch of chunks 2 it and
+// 2 it + 1.  Loads: all kHpBatch global loads of a lane are issued before
+// the first LDS write (out-of-range lanes load the channel's first sample and
+// write 0), so a wave has the whole batch in flight; stores: the batch is
+// read from LDS first, then stored.
 template <bool LOAD>
 __device__ __forceinline__ void hp_batch_move(float* __restrict__ g, float (*buf)[kHpBatch + 1], int kbase, int off,
                                               const RoomDesc* R) {
+    static_assert(kHpBatch == 32, "two chunks per instruction");
     const int lane = threadIdx.x;
-#pragma unroll 4
-    for (int it = 0; it < kHpBatch; ++it) {
-        const int e = it * 64 + lane;
-        const int c = e / kHpBatch, i = e % kHpBatch;
-        const int kc = kbase + c;
-        const int n = kc * kHpChunk + off + i;
-        const bool ok = kc < R->n_chunks && n < R->T;
-        if constexpr (LOAD) {
-            buf[c][i] = ok ? g[n] : 0.0f;
-        } else {
-            if (ok) g[n] = buf[c][i];
+    const int i = lane & (kHpBatch - 1), half = lane / kHpBatch;
+    float v[kHpBatch];
+    if constexpr (LOAD) {
+#pragma unroll
+        for (int it = 0; it < kHpBatch; ++it) {
+            const int kc = kbase + 2 * it + half;
+            const int n = kc * kHpChunk + off + i;
+            const bool ok = kc < R->n_chunks && n < R->T;
+            v[it] = g[ok ? static_cast<unsigned>(n) : 0u];
+        }
+#pragma unroll
+        for (int it = 0; it < kHpBatch; ++it) {
+            const int kc = kbase + 2 * it + half;
+            const int n = kc * kHpChunk + off + i;
+            const bool ok = kc < R->n_chunks && n < R->T;
+            buf[2 * it + half][i] = ok ? v[it] : 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < kHpBatch; ++it) v[it] = buf[2 * it + half][i];
+#pragma unroll
+        for (int it = 0; it < kHpBatch; ++it) {
+            const int kc = kbase + 2 * it + half;
+            const int n = kc * kHpChunk + off + i;
+            if (kc < R->n_chunks && n < R->T) g[n] = v[it];
         }
     }
 }
@@ -1441,13 +1461,28 @@ __global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ d
         for (int local = threadIdx.x; local < R->n_src * R->n_mic; local += blockDim.x) {
             const int64_t c0 = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks;
             double s0 = 0.0, s1 = 0.0;
-            for (int k = 0; k < R->n_chunks; ++k) {
-                init[2 * (c0 + k)] = s0;
-                init[2 * (c0 + k) + 1] = s1;
-                const double n0 = zend[2 * (c0 + k)] + (p0 * s0 + p1 * s1);
-                const double n1 = zend[2 * (c0 + k) + 1] + (p2 * s0 + p3 * s1);
-                s0 = n0;
-                s1 = n1;
+            // the zero-state ends of kCarryAhead chunks are loaded together, so
+            // that the recurrence waits for memory once per group of chunks
+            constexpr int kCarryAhead = 16;
+            for (int k0 = 0; k0 < R->n_chunks; k0 += kCarryAhead) {
+                double2 z[kCarryAhead];
+#pragma unroll
+                for (int j = 0; j < kCarryAhead; ++j) {
+                    const int k = min(k0 + j, R->n_chunks - 1);
+                    z[j] = reinterpret_cast<const double2*>(zend)[c0 + k];
+                }
+#pragma unroll
+                for (int j = 0; j < kCarryAhead; ++j) {
+                    const int k = k0 + j;
+                    if (k < R->n_chunks) {
+                        init[2 * (c0 + k)] = s0;
+                        init[2 * (c0 + k) + 1] = s1;
+                        const double n0 = z[j].x + (p0 * s0 + p1 * s1);
+                        const double n1 = z[j].y + (p2 * s0 + p3 * s1);
+                        s0 = n0;
+                        s1 = n1;
+                    }
+                }
             }
         }
     }
