@@ -189,6 +189,30 @@ def test_render_config3_long_filters_sampled():
     say(f"config3 worst rel L2 {worst:.3e}")
 
 
+def test_render_config5_mixed_full_sampled():
+    """The mixed stream at full size (1,024 rooms: 16 and 48 kHz, 2-8
+    microphones, 1-3 sources, T60 up to 1 s) in its tuned launch shape;
+    sampled rooms against the oracle: the first and last, one with 2
+    microphones and 1 source, one with 8 microphones and 3 sources, and the
+    one with the most output samples (48 kHz, 3 x 8 channels, T60 0.98 s)."""
+    from paper_2304_08052_amd import autotune
+    torch, fr = _torch(), _fr()
+    batch = W.config5(0)
+    launch = autotune.launch_for(batch)
+    say(f"render config5 B=1024 mixed (sampled rooms) launch={launch}")
+    plan = fr.Plan(batch, launch=launch)
+    out, _ = plan.forward()
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(out.cpu().numpy()))
+    rooms = F.rooms_from_batch(batch)
+    heaviest = max(range(len(rooms)), key=lambda b: len(rooms[b].src) * len(rooms[b].mic) *
+                   F.rir_length(rooms[b].rt60, rooms[b].fs))
+    small = next(b for b, r in enumerate(rooms) if len(r.mic) == 2 and len(r.src) == 1)
+    large = next(b for b, r in enumerate(rooms) if len(r.mic) == 8 and len(r.src) == 3)
+    worst = check_rooms(plan, out, batch, [0, small, large, heaviest, 511, 1023])
+    say(f"config5 worst rel L2 {worst:.3e}")
+
+
 def test_render_perturbed_inputs_table_fixed():
     torch, fr = _torch(), _fr()
     say("render with perturbed mics and r, table fixed")
