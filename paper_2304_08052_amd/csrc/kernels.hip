@@ -1463,7 +1463,7 @@ __global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ d
             double s0 = 0.0, s1 = 0.0;
             // the zero-state ends of kCarryAhead chunks are loaded together, so
             // that the recurrence waits for memory once per group of chunks
-            constexpr int kCarryAhead = 16;
+            constexpr int kCarryAhead = 32;
             for (int k0 = 0; k0 < R->n_chunks; k0 += kCarryAhead) {
                 double2 z[kCarryAhead];
 #pragma unroll
