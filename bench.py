@@ -670,6 +670,63 @@ def run_multirate(args, batch, desc, launch):
     print(json.dumps(line), flush=True)
 
 
+def _event_ms(fn, reps=10, warmup=3):
+    """Milliseconds per call of fn (stream-ordered work) by HIP events on the
+    current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def mixed_size_classes(launch):
+    """The mixed stream by size class: the 16 kHz and the 48 kHz rooms of its
+    first batch, each as a batch of its own in the stream's launch shape, timed
+    as eager forward and forward + backward calls.  Per class: RIR/s of the
+    forward + backward, and the forward's algorithmic fractions of the FP32
+    peak (11 flops per tap-update) and of the HBM bandwidth (output written)."""
+    import numpy as np
+    import torch
+    from paper_2304_08052_amd import framrir as fr
+    from paper_2304_08052_amd import workloads as W
+    rooms = fr.split_rooms(W.config5(0))
+    classes = []
+    for fs in (16000.0, 48000.0):
+        keep = [r for r in rooms if float(r["fs"][0]) == fs]
+        sub = {k: np.concatenate([r[k] for r in keep]) for k in keep[0]}
+        plan = fr.Plan(sub, launch=launch)
+        info = plan.info
+        ws = plan.workspace(backward=True)
+        table, out = plan.empty_table(), plan.empty_out()
+        grad = torch.from_numpy(W.upstream_grad(info.out_floats, seed=7)).cuda()
+
+        def fwd():
+            plan.forward(table=table, out=out, ws=ws)
+
+        def fwd_bwd():
+            fwd()
+            plan.backward(table, grad, ws=ws, prepared=True)
+
+        fwd_ms, fb_ms = _event_ms(fwd), _event_ms(fwd_bwd)
+        taps = int(np.sum(plan.n_img.astype(np.int64) * np.repeat(sub["n_mic"], sub["n_src"]))) * fr.FRAMRIR_TAPS
+        classes.append({
+            "class": f"fs {fs / 1000:g} kHz", "rooms": len(keep), "rirs": int(info.n_src),
+            "samples_out": int(info.out_floats), "fwd_ms": fwd_ms, "fwd_bwd_ms": fb_ms,
+            "rirs_per_s_fwd_bwd": info.n_src / (fb_ms * 1e-3),
+            "fwd_valu_frac_algorithmic": taps * FLOPS_PER_TAP / (fwd_ms * 1e-3) / 1e12 / FP32_NONPACKED_PEAK_TFLOPS,
+            "fwd_hbm_write_frac": info.out_floats * 4 / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        })
+    return classes
+
+
 def run_mixed(args, batch0, desc, launch):
     """Mixed on-the-fly stream: every step renders a new batch of 1024 rooms
     (fs 16/48 kHz, 2-8 mics, 1-3 sources, T60 0.1-1.0 s) through one
@@ -721,6 +778,7 @@ def run_mixed(args, batch0, desc, launch):
                    "rirs_per_step": n_rirs / args.steps, "launch": gs.launch,
                    "capacity_out_floats": int(gs.cap.info.out_floats)},
         "plan_host_ms_per_batch": plan_ms,
+        "size_classes": mixed_size_classes(gs.launch),
     }
     print(json.dumps(line), flush=True)
 
