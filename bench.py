@@ -173,6 +173,18 @@ def _oracle_rooms(sub):
     return 0
 
 
+def host_cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(batch, n_rooms):
     """The FP64 oracle as it stands, on the first n_rooms rooms, one thread."""
     import numpy as np
@@ -185,7 +197,7 @@ def cpu_baseline(batch, n_rooms):
         t0 = time.perf_counter()
         F.simulate(sub)
         dt = time.perf_counter() - t0
-    return dict(value=ns / dt, unit="RIR/s", cores=1, kind="oracle",
+    return dict(value=ns / dt, unit="RIR/s", cores=1, kind="oracle", cpu_model=host_cpu_model(),
                 sample=f"first {nb} rooms ({ns} multi-channel RIRs) of the same workload, "
                        f"FP64 numpy oracle, {dt:.2f} s on 1 thread")
 
@@ -204,7 +216,7 @@ def cpu_baseline_parallel(batch, n_rooms):
         t0 = time.perf_counter()
         pool.map(_oracle_rooms, subs, chunksize=1)
         dt = time.perf_counter() - t0
-    return dict(value=ns / dt, unit="RIR/s", cores=workers, kind="oracle",
+    return dict(value=ns / dt, unit="RIR/s", cores=workers, kind="oracle", cpu_model=host_cpu_model(),
                 sample=f"first {nb} rooms ({ns} multi-channel RIRs) of the same workload, "
                        f"FP64 numpy oracle, {dt:.2f} s on {workers} single-threaded processes")
 
