@@ -1839,7 +1839,10 @@ int launch_backward(const framrir_plan* plan, const void* desc_dev, const double
                        static_cast<long long>(plan->ws_bwd_bytes));
     const RenderWs w = render_ws(plan, ws_dev);
     float* partials = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + plan->ws_part_off);
-    const int nt = plan->launch.bwd_wg_threads;
+    // Through the draws the kernel runs at 4 waves per SIMD; there two
+    // 512-thread workgroups per CU finish the persistent queue sooner than
+    // one 1024-thread workgroup, so larger workgroups are capped at 512.
+    const int nt = draws ? std::min(plan->launch.bwd_wg_threads, 512) : plan->launch.bwd_wg_threads;
     const int red_floats = (draws ? bwd_values<true>() : bwd_values<false>()) + 1;
     const int lds = std::max(plan->launch.lds_bytes, 4 * red_floats * nt);
     const dim3 grid(plan->bwd_grid), block(nt);
