@@ -1,0 +1,94 @@
+"""A pool of worker processes for the FP64 oracle in the GPU parity tests.
+
+The pool is forked once, at the end of collection, before any test touches
+the GPU (conftest.py starts it when a selected test asks for the
+``oracle_pool`` fixture), so its workers hold no GPU state.  Each worker runs
+single-threaded numpy.  The work functions below take one room as a
+single-room batch (paper_2304_08052_amd.framrir.split_rooms), compute the
+oracle's RIRs or adjoint for it and compare them with the GPU's values sent
+along, returning only the errors.
+"""
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+_POOL = None
+
+
+def workers():
+    """Host cores to use: the process's CPU set, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _init_worker():
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except ImportError:      # pragma: no cover
+        pass
+
+
+def start():
+    global _POOL
+    if _POOL is None:
+        _POOL = mp.get_context("fork").Pool(workers(), initializer=_init_worker)
+    return _POOL
+
+
+def get():
+    if _POOL is None:
+        raise RuntimeError("the oracle pool is started at collection time, before the GPU is used")
+    return _POOL
+
+
+def stop():
+    global _POOL
+    if _POOL is not None:
+        _POOL.terminate()
+        _POOL.join()
+        _POOL = None
+
+
+def rel_l2(got, want):
+    den = np.linalg.norm(want)
+    return float(np.linalg.norm(got - want) / den) if den > 0 else float(np.linalg.norm(got))
+
+
+def _room(one):
+    from oracle import framrir as F
+    rm = F.rooms_from_batch(one)[0]
+    return F, rm, F.room_plan(rm, F.Params())
+
+
+def forward_errors(job):
+    """job = (one-room batch, GPU RIRs [S, M, T] FP32): per-channel relative
+    L2 errors [S, M] against the oracle's render (Eq. 1, 8)."""
+    one, got = job
+    F, rm, op = _room(one)
+    want = F.render_room(op, rm)
+    got = np.asarray(got, dtype=np.float64).reshape(want.shape)
+    return np.array([[rel_l2(got[s, m], want[s, m]) for m in range(want.shape[1])]
+                     for s in range(want.shape[0])])
+
+
+def backward_errors(job):
+    """job = (one-room batch, dL/dh [S, M, T] FP32, GPU grad_mic [M, 3],
+    grad_src [S, 3], grad_r): relative errors of the three gradients against
+    the oracle's adjoint with the draws held fixed."""
+    one, g, gm, gs, gr = job
+    F, rm, op = _room(one)
+    wm, ws, wr = F.adjoint_room(op, rm, np.asarray(g, dtype=np.float64).reshape(len(rm.src), len(rm.mic), op["T"]))
+    return (rel_l2(np.ravel(gm), np.ravel(wm)), rel_l2(np.ravel(gs), np.ravel(ws)),
+            float(abs(gr - wr) / abs(wr)) if wr != 0 else float(abs(gr)))
+
+
+def room_errors(job):
+    """Forward and backward errors of one room: job = (one-room batch, RIRs,
+    dL/dh, grad_mic, grad_src, grad_r); the backward part is skipped when
+    dL/dh is None."""
+    one, got, g, gm, gs, gr = job
+    fwd = forward_errors((one, got))
+    bwd = backward_errors((one, g, gm, gs, gr)) if g is not None else None
+    return fwd, bwd

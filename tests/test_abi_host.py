@@ -69,6 +69,14 @@ def test_host_philox_bit_exact_vs_oracle():
     assert np.array_equal(got.astype(np.uint64), want)
 
 
+def test_host_philox_known_answer_vectors():
+    from tests.golden import philox_kat
+    for width, ctr, key, want in philox_kat():
+        if width != 32:
+            continue
+        got = fr.host_philox4x32(np.array([ctr], dtype=np.uint32), np.array([key], dtype=np.uint32))
+        assert [int(v) for v in got[0]] == want
+
 @pytest.mark.parametrize("maker", [W.config1, lambda: W.config2(16), lambda: W.config3(4),
                                    lambda: W.small_mixed(8, seed=3)])
 def test_plan_scalars_bit_equal_oracle(maker):

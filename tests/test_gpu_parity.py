@@ -76,6 +76,18 @@ def test_philox_words_bit_exact():
     assert np.array_equal(got, want)
 
 
+def test_philox_known_answer_vectors():
+    torch, fr = _torch(), _fr()
+    from tests.golden import philox_kat
+    rows = [r for r in philox_kat() if r[0] == 32]
+    ctr = np.array([r[1] for r in rows], dtype=np.uint32)
+    key = np.array([r[2] for r in rows], dtype=np.uint32)
+    out = fr.philox4x32(torch.from_numpy(ctr.view(np.int32)).cuda(), torch.from_numpy(key.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    assert [[int(v) for v in g] for g in got] == [r[3] for r in rows]
+
+
 def test_cbrt_bit_exact():
     torch, fr = _torch(), _fr()
     say("cbrt 2e5 arguments")

@@ -126,14 +126,21 @@ def test_reflection_count_without_perturbation():
 
 @pytest.mark.parametrize("tau", [0.25, 0.5, 1.0])
 def test_perturbation_scales_with_dr_tau(tau):
-    # with the distance term removed (RR_max = 1 -> g is clamped to 1) this is
-    # not visible; use a huge RR_max so no clamp is active and read p DR^tau
-    prm = F.Params(tau=tau)
-    dr, ct = _draws(prm=prm, rrmax=1e9)
-    base = 1.0 + (dr["dist"] / ct) ** 2 * (1e9 - 1.0)
-    pert = dr["g"] - base
-    ok = dr["g"] > 1.0
-    assert np.allclose(pert[ok], dr["p"][ok] * dr["dr"][ok] ** tau, rtol=0, atol=1e-6 * 1e9 * 1e-6)
+    # Eq. 6 with a constant perturbation p = a = b = 1e-3 and RR_max = 1000:
+    # g - (1 + (D/cT)^2 (RR_max - 1)) must be p DR^tau.  The distance term is
+    # below 1000, so the difference carries an absolute rounding error of at
+    # most ~2.3e-13 against a perturbation of at least 1e-3: checked to 1e-9
+    # relative against DR^tau from the C library's pow, so a perturbation
+    # scaled by D instead of DR, a wrong tau or a dropped term fails.
+    prm = F.Params(tau=tau, a=1e-3, b=1e-3)
+    dr, ct = _draws(prm=prm, rrmax=1000.0)
+    base = 1.0 + (dr["dist"] / ct) ** 2 * 999.0
+    ok = dr["g"] < 1000.0
+    assert ok.sum() > 0.9 * ok.size
+    want = np.array([1e-3 * math.pow(v, tau) for v in dr["dr"][ok]])
+    pert = dr["g"][ok] - base[ok]
+    assert np.all(np.abs(pert - want) <= 1e-9 * want)
+    assert np.all(dr["p"] == 1e-3)
 
 
 def test_draws_are_counter_based():

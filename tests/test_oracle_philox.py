@@ -6,13 +6,17 @@
 * the Weyl key increments equal their closed-form definition (fixed-point
   golden ratio and sqrt(3) - 1) at both widths;
 * the vectorised W = 32 version equals the generic one at W = 32;
-* the W = 32 output is uniform (chi-square) and avalanches.
+* the W = 32 output is uniform (chi-square) and avalanches;
+* both widths reproduce the published known-answer vectors of Philox4x32-10
+  and Philox4x64-10 (tests/golden/philox_kat.txt), which fixes the
+  multipliers and every other constant to the generator's definition.
 """
 import numpy as np
 import pytest
 from scipy import stats
 
 from oracle.philox import MULTIPLIERS, WEYL, philox4_ref, philox4x32, weyl_constant
+from tests.golden import philox_kat
 
 
 @pytest.mark.parametrize("key", [(0, 0), (1, 2), (0xDEADBEEFCAFEF00D, 0x0123456789ABCDEF)])
@@ -33,6 +37,20 @@ def test_generic_w64_matches_numpy_philox(key):
 def test_weyl_constants_closed_form():
     for width in (32, 64):
         assert WEYL[width] == (weyl_constant("golden", width), weyl_constant("sqrt3", width))
+
+
+def test_known_answer_vectors_both_widths():
+    rows = philox_kat()
+    assert sorted({r[0] for r in rows}) == [32, 64] and len(rows) == 6
+    for width, ctr, key, want in rows:
+        assert list(philox4_ref(ctr, key, width=width)) == want, (width, ctr)
+
+
+def test_known_answer_vectors_vectorised_w32():
+    for width, ctr, key, want in philox_kat():
+        if width == 32:
+            got = philox4x32(*[np.array([c], dtype=np.uint64) for c in ctr + key])
+            assert [int(w[0]) for w in got] == want
 
 
 def test_multipliers_are_odd_and_full_width():
