@@ -314,7 +314,7 @@ int framrir_early(const framrir_plan* plan, const void* desc_dev, const double* 
  * r_l fs with the 81-tap Hann-windowed sinc (unit peak) into inter_dev[0 ..
  * mr_floats) (packed [S][M][T_l], T_l = ceil(T60 r_l fs)), an 80 Hz
  * second-order Butterworth high-pass (bilinear, prewarped; FP64 recurrence,
- * exact chunked evaluation, its zero-state chunks in inter_dev[mr_floats ..
+ * exact chunked evaluation, its partial chunk responses in inter_dev[mr_floats ..
  * 2 mr_floats) as scratch), and the decimation by r_l with the same pulse in
  * units of fs: out_dev (out_floats FP32, packed [S][M][T], T = ceil(T60 fs)).
  * inter_dev: 2 * mr_floats FP32; ws_dev: ws_mr_bytes, initialised as for

@@ -1321,10 +1321,17 @@ __global__ void __launch_bounds__(256) early_kernel(const void* __restrict__ des
 // ---------------------------------------------------------------------------
 // High-pass y[n] = b0 (x[n] - 2 x[n-1] + x[n-2]) - a1 y[n-1] - a2 y[n-2] (FP64)
 // over chunks of kHpChunk samples evaluated in parallel and exactly: every
-// chunk is first filtered from a zero state (its input history is known), the
-// true initial states are then carried from chunk to chunk through the
-// chunk's state transition phi, and each chunk adds the unforced response of
-// its initial state.  One wave per 64 consecutive chunks of a channel (lane =
+// chunk is first filtered with its true input history and its output history
+// set equal to that input history, (y[s-1], y[s-2]) := (x[s-1], x[s-2]); the
+// deviations d = y - x of the true output states at the chunk starts are then
+// carried from chunk to chunk through the chunk's state transition phi, and
+// each chunk adds the unforced response of its deviation.  (Starting from
+// y = x rather than y = 0 keeps the stored FP32 part of the size of the
+// output: from a zero output state the slow poles near z = 1 make the partial
+// response grow across the chunk, about the chunk length times the input's
+// slope at its start, and the unforced response cancels that growth, leaving
+// the FP32 rounding of the partial response amplified by that cancellation.)
+// One wave per 64 consecutive chunks of a channel (lane =
 // chunk); batches of kHpBatch samples go through LDS, so that the global
 // loads and stores are whole 128-byte lines while each lane runs its chunk's
 // recurrence.  Blocks: (chunks / 64, rooms, channels of the room).
@@ -1386,9 +1393,10 @@ __global__ void __launch_bounds__(64) hp_zero_state_kernel(const void* __restric
             const bool live = k < R->n_chunks;
             const int s0 = k * kHpChunk, s1 = min(R->T, s0 + kHpChunk);
             const double b0 = R->hp_b0, a1 = R->hp_a1, a2 = R->hp_a2;
-            double x1 = 0.0, x2 = 0.0, y1 = 0.0, y2 = 0.0;
+            double x1 = 0.0, x2 = 0.0;
             if (live && s0 >= 1) x1 = x[base + s0 - 1];
             if (live && s0 >= 2) x2 = x[base + s0 - 2];
+            double y1 = x1, y2 = x2;   // output history := input history
             for (int off = 0; off < kHpChunk; off += kHpBatch) {
                 __syncthreads();
                 hp_batch_move<true>(const_cast<float*>(x) + base, buf, kbase, off, R);
@@ -1409,8 +1417,11 @@ __global__ void __launch_bounds__(64) hp_zero_state_kernel(const void* __restric
             }
             if (live) {
                 const int64_t ci = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks + k;
-                zend[2 * ci] = y1;
-                zend[2 * ci + 1] = y2;
+                // deviation y - x of the partial response's end state: the
+                // next chunk's starting deviation is this plus phi times this
+                // chunk's starting deviation
+                zend[2 * ci] = y1 - x1;
+                zend[2 * ci + 1] = y2 - x2;
             }
         }
     }
@@ -1418,9 +1429,9 @@ __global__ void __launch_bounds__(64) hp_zero_state_kernel(const void* __restric
 
 // Per room: the unforced responses ha, hb of the high-pass over one chunk
 // from the states (y[-1], y[-2]) = (1, 0) and (0, 1), and the phase-major
-// decimation taps; then the initial state (y[s-1], y[s-2]) of every chunk,
-// one thread per channel, chunk after chunk:
-// end(k) = zero-state end(k) + phi init(k).
+// decimation taps; then the initial deviation (y - x at s-1, s-2) of every
+// chunk, one thread per channel, chunk after chunk:
+// init(k + 1) = partial end deviation(k) + phi init(k).
 
 __global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ desc, const double* __restrict__ zend,
                                                       double* __restrict__ init, double* __restrict__ basis,
@@ -1461,7 +1472,7 @@ __global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ d
         for (int local = threadIdx.x; local < R->n_src * R->n_mic; local += blockDim.x) {
             const int64_t c0 = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks;
             double s0 = 0.0, s1 = 0.0;
-            // the zero-state ends of kCarryAhead chunks are loaded together, so
+            // the partial end deviations of kCarryAhead chunks are loaded together, so
             // that the recurrence waits for memory once per group of chunks
             constexpr int kCarryAhead = 32;
             for (int k0 = 0; k0 < R->n_chunks; k0 += kCarryAhead) {
@@ -1491,7 +1502,7 @@ __global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ d
 
 // Decimation by r_l (Sec. II): out[n] = sum_j x[j] P((n r_l - j) / r_l), the
 // 81-tap Hann-windowed sinc in units of fs.  x is the high-passed signal: the
-// zero-state chunks y0 plus, per chunk k >= 1, init(k) . (ha, hb), added
+// partial chunk responses y0 plus, per chunk k >= 1, init(k) . (ha, hb), added
 // while the tile's input span is staged into LDS (zero outside [0, T_l)).  One
 // block per (tile of kDecOut outputs, room, channel); each thread R
 // consecutive outputs.  With w = r r_l - u, output r reads span[R tid r_l +

@@ -489,8 +489,8 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     plan->ws_bytes = align(plan->ws_rows_off + static_cast<int64_t>(4 * sizeof(double)) * img_off);
     plan->ws_part_off = plan->ws_bytes;
     plan->ws_bwd_bytes = plan->ws_part_off + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
-    // multi-rate: per high-pass chunk its zero-state end (2 doubles) and its
-    // initial state (2 doubles)
+    // multi-rate: per high-pass chunk the end deviation y - x of its partial
+    // response (2 doubles) and its initial deviation (2 doubles)
     plan->ws_zend_off = align(plan->ws_bytes);
     plan->ws_init_off = align(plan->ws_zend_off + 16 * chunk_row);
     plan->ws_basis_off = align(plan->ws_init_off + 16 * chunk_row);
