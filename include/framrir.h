@@ -218,6 +218,27 @@ int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* tabl
                     const double* mic_dev, const double* src_dev, const double* r_dev,
                     float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * framrir_forward with its workspace in a static device array of the library,
+ * FRAMRIR_NOALLOC_SCRATCH_BYTES (64 MiB) per device, held by every device
+ * the library runs on until the process ends (its address is looked up once
+ * per device, on the first call with that device current).  Arguments, the
+ * table and the outputs as for framrir_forward; the caller still owns the
+ * table, positions and output.  The call allocates nothing and enqueues a
+ * small kernel that clears the workspace's counters, then the preparation
+ * (with the draws) and the render.  Every call on one device shares that
+ * device's array, which keeps the last call's contents: calls that overlap on
+ * one device (other streams, other threads, or any framrir_forward_noalloc
+ * still running) race and give wrong results.  Errors: WORKSPACE when the
+ * plan's ws_bytes exceeds FRAMRIR_NOALLOC_SCRATCH_BYTES (nothing enqueued:
+ * use framrir_forward with a caller workspace, or split the batch),
+ * UNSUPPORTED for a multi-rate plan, and as framrir_forward. */
+#define FRAMRIR_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int framrir_forward_noalloc(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                            const double* mic_dev, const double* src_dev, const double* r_dev,
+                            float* out_dev, void* stream);
+
 /* The two halves of framrir_render.  framrir_prepare (one workgroup per
  * source) computes, into the workspace, each source's fixed-point scale (a
  * bound on the sum of its pulse amplitudes over the microphones) and a copy

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 
 #include "../../include/framrir.h"
@@ -1806,6 +1807,73 @@ extern "C" int framrir_forward(const framrir_plan* plan, const void* desc_dev, d
     if (rc) return rc;
     return framrir_render_prepared(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws_dev, ws_bytes,
                                    stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward: framrir_forward with its workspace in a static
+// device array of the library, for callers that cannot allocate.
+// ---------------------------------------------------------------------------
+// The array itself; each device that runs the library holds its own copy
+// until the process ends.  Host code never passes its name to a kernel (on the
+// host the name is only a stand-in): it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[FRAMRIR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device
+// (with that device current) and kept.
+int current_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fr_fail(FRAMRIR_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fr_fail(FRAMRIR_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                           hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return FRAMRIR_OK;
+}
+
+}  // namespace
+
+extern "C" int framrir_forward_noalloc(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                                       const double* mic_dev, const double* src_dev, const double* r_dev,
+                                       float* out_dev, void* stream) {
+    if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL plan");
+    if (plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
+    if (plan->ws_bytes > static_cast<int64_t>(FRAMRIR_NOALLOC_SCRATCH_BYTES))
+        return fr_fail(FRAMRIR_E_WORKSPACE,
+                       "the plan needs %lld workspace bytes, the static scratch holds %lld: use framrir_forward "
+                       "with a caller workspace, or split the batch",
+                       static_cast<long long>(plan->ws_bytes),
+                       static_cast<long long>(FRAMRIR_NOALLOC_SCRATCH_BYTES));
+    void* ws = nullptr;
+    int rc = current_scratch(&ws);
+    if (rc) return rc;
+    // every argument checked before anything is enqueued
+    rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws,
+                           static_cast<size_t>(FRAMRIR_NOALLOC_SCRATCH_BYTES), plan->ws_bytes);
+    if (rc) return rc;
+    // the persistent grid's counters start at zero: cleared by a kernel (not
+    // a memset node, so that the call can be captured), every call
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, static_cast<int*>(ws));
+    if ((rc = check_launch("zero_counters_kernel"))) return rc;
+    if ((rc = launch_prepare(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, ws, st, true))) return rc;
+    return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws, st);
 }
 
 namespace {

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libframrir.so")
 
 FRAMRIR_TAPS = 81
 FRAMRIR_FLAG_MULTIRATE = 1
+NOALLOC_SCRATCH_BYTES = 64 << 20      # FRAMRIR_NOALLOC_SCRATCH_BYTES
 
 
 class FramrirError(RuntimeError):
@@ -65,6 +66,7 @@ EXPORTS = {
     "framrir_draw": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "framrir_render": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_forward": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "framrir_forward_noalloc": (ctypes.c_int, [ctypes.c_void_p] * 8),
     "framrir_prepare": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                                                ctypes.c_void_p]),
     "framrir_render_prepared": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
@@ -253,6 +255,17 @@ class Plan:
         desc = self.desc if desc is None else desc
         _check(lib().framrir_forward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
                                      _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out, table
+
+    def forward_noalloc(self, table, out, mic=None, src=None, r=None, stream=None, desc=None):
+        """framrir_forward_noalloc: the forward with the library's static
+        device scratch as its workspace (no allocation in the call; the
+        caller passes the table and the output)."""
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_forward_noalloc(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                             _ptr(out), _stream(stream)))
         return out, table
 
     def prepare(self, table, mic=None, src=None, r=None, ws=None, draw=False, stream=None, desc=None):
