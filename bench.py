@@ -24,18 +24,29 @@ if HERE not in sys.path:
 
 METRIC = "multi-channel RIRs/sec at batch 256, 16 kHz; fwd+bwd/fwd ratio; VALU/HBM % peak"
 
-# MI355X peaks.  HBM3E: 8 TB/s.  FP32 vector: 157.3 TFLOP/s is the published
-# figure with packed FP32 instructions, which this library never emits; the
-# reachable non-packed rate is 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz.
+# MI355X peaks (published): HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s (that
+# figure counts packed FP32 instructions, which this library never emits: the
+# non-packed rate is 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz = 78.64,
+# reported beside it); dense fp16 matrix 2.5 PFLOP/s.
 HBM_PEAK_GBS = 8000.0
-FP32_NONPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.64
 FP32_PUBLISHED_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.64
+FP16_MFMA_PEAK_TFLOPS = 2500.0
 FLOPS_PER_TAP = 11          # sub, rcp, 2 mul + FMA (window), FMA, mul, add
+# bin-moment render: per 256-sample block 31 MFMA 16x16x32 (16,384 flops each)
+MOMENT_MFMA_PER_BLOCK = 31
+MOMENT_BLOCK = 256
 
 
 KERNEL_SOURCES = ["kernels.hip", "framrir_internal.h", "tap_poly.h", "plan.cpp", "plan_internal.h"]
-HBM_PROFILE = os.path.join(HERE, "profiles", "render_kernel_batched256_hbm.md")
-VALU_PROFILE = os.path.join(HERE, "profiles", "render_kernel_batched256_valu.md")
+PROFILES = {   # committed counter summaries per render path
+    0: dict(hbm=os.path.join(HERE, "profiles", "render_kernel_batched256_hbm.md"),
+            valu=os.path.join(HERE, "profiles", "render_kernel_batched256_valu.md")),
+    1: dict(hbm=os.path.join(HERE, "profiles", "render_moment_kernel_batched256_hbm.md"),
+            valu=os.path.join(HERE, "profiles", "render_moment_kernel_batched256_valu.md")),
+}
+HBM_PROFILE = PROFILES[0]["hbm"]
+VALU_PROFILE = PROFILES[0]["valu"]
 SPATIAL_SOURCES = ["spatial.hip", "framrir_internal.h", "plan_internal.h"]
 SPATIAL_HBM_PROFILE = os.path.join(HERE, "profiles", "spatial_batched256_hbm.md")
 
@@ -74,6 +85,14 @@ def measured_spatial_traffic():
     return int(kv["traffic_bytes"])
 
 
+def launch_key(launch):
+    """The launch shape as the counter summaries record it."""
+    keys = ["lds_bytes", "wg_threads", "grid_wgs", "max_mic_group", "waves_per_simd"]
+    if launch.get("render_path", 0):
+        keys.append("render_path")
+    return " ".join(f"{k}={launch[k]}" for k in keys)
+
+
 def profile_values(path, workload_name, launch):
     """The key = value lines of a committed rocprofv3 counter summary, or None
     when the kernel sources, the workload or the launch shape differ from the
@@ -83,25 +102,34 @@ def profile_values(path, workload_name, launch):
             kv = dict(line.split(" = ", 1) for line in f.read().splitlines() if " = " in line)
     except OSError:
         return None
-    shape = " ".join(f"{k}={launch[k]}" for k in ("lds_bytes", "wg_threads", "grid_wgs", "max_mic_group",
-                                                  "waves_per_simd"))
-    if (kv.get("workload") != workload_name or kv.get("launch") != shape
+    if (kv.get("workload") != workload_name or kv.get("launch") != launch_key(launch)
             or kv.get("source_sha256") != kernel_sources_sha256()):
         return None
     return kv
 
 
+def _profile_path(kind, launch, default):
+    path = PROFILES.get(launch.get("render_path", 0), PROFILES[0])[kind]
+    return default if launch.get("render_path", 0) == 0 else path
+
+
 def measured_traffic(workload_name, launch):
-    """HBM bytes per render launch from the committed FETCH_SIZE and WRITE_SIZE
-    passes (scaled by a copy kernel of known size), or None (profile_values)."""
-    kv = profile_values(HBM_PROFILE, workload_name, launch)
+    """HBM bytes per render launch and of the whole forward step (preparation
+    + render) from the committed FETCH_SIZE and WRITE_SIZE passes (scaled by
+    a copy kernel of known size), or None (profile_values)."""
+    kv = profile_values(_profile_path("hbm", launch, HBM_PROFILE), workload_name, launch)
     return int(kv["traffic_bytes"]) if kv else None
+
+
+def measured_step_traffic(workload_name, launch):
+    kv = profile_values(_profile_path("hbm", launch, HBM_PROFILE), workload_name, launch)
+    return int(kv["step_traffic_bytes"]) if kv and "step_traffic_bytes" in kv else None
 
 
 def measured_valu_insts(workload_name, launch):
     """VALU and LDS wave instructions per render launch from the committed
     SQ counter pass, or None (profile_values)."""
-    kv = profile_values(VALU_PROFILE, workload_name, launch)
+    kv = profile_values(_profile_path("valu", launch, VALU_PROFILE), workload_name, launch)
     return (int(kv["valu_wave_insts"]), int(kv["lds_wave_insts"])) if kv else None
 
 
@@ -112,8 +140,9 @@ def parse_args():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--workload", default="batched", choices=["batched", "long", "mixed", "one", "multirate",
                                                               "spatial"])
-    p.add_argument("--cpu-rooms", type=int, default=192,
-                   help="rooms of the workload timed through the FP64 oracle on one host core (0 = skip)")
+    p.add_argument("--cpu-rooms", type=int, default=256,
+                   help="rooms of the workload timed through the FP64 oracle (one host core, then all host "
+                        "cores; 0 = skip)")
     p.add_argument("--no-graph", action="store_true")
     p.add_argument("--no-backward", action="store_true")
     p.add_argument("--lds-bytes", type=int, default=None)
@@ -123,9 +152,11 @@ def parse_args():
     p.add_argument("--grid-wgs", type=int, default=None, help="workgroups of the persistent grid (0 = as many as fit)")
     p.add_argument("--bwd-wg-threads", type=int, default=None, help="threads per backward workgroup (0 = as the render)")
     p.add_argument("--bwd-grid-wgs", type=int, default=None, help="workgroups of the backward grid (0 = as many as fit)")
+    p.add_argument("--render-path", type=int, default=None, choices=[0, 1],
+                   help="render path: 0 scatter, 1 bin moments on the matrix cores")
     p.add_argument("--tune", action="store_true", help="pick the launch shape with the autotuner first")
-    p.add_argument("--per-room", action="store_true",
-                   help="also time the plain per-room launch path on the same batch")
+    p.add_argument("--no-per-room", action="store_true",
+                   help="skip the plain per-room launch path (the same kernels, one launch set per room)")
     p.add_argument("--early", action="store_true",
                    help="also time the early-reverberation windows (Eq. 9) of the rendered batch")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -247,6 +278,8 @@ def main():
         launch["bwd_wg_threads"] = args.bwd_wg_threads
     if args.bwd_grid_wgs is not None:
         launch["bwd_grid_wgs"] = args.bwd_grid_wgs
+    if args.render_path is not None:
+        launch["render_path"] = args.render_path
     if args.workload == "spatial":
         return run_spatial(args, launch)
     batch, desc = workload(args.workload)
@@ -256,7 +289,13 @@ def main():
         return run_multirate(args, batch, desc, launch)
     # the oracle on all host cores first: its worker processes fork before
     # anything here touches the GPU
-    cpu_par = cpu_baseline_parallel(batch, args.cpu_rooms) if args.cpu_rooms > 0 else None
+    cpu_par = cpu_long = None
+    if args.cpu_rooms > 0:
+        cpu_par = cpu_baseline_parallel(batch, args.cpu_rooms)
+        if args.workload == "batched":
+            long_batch, _ = workload("long")
+            cpu_long = cpu_baseline_parallel(long_batch, len(long_batch["rt60"]))
+            cpu_long["workload"] = "long filters: 64 rooms, 48 kHz, 8 mics, T60 0.6-1.2 s"
     tuned = None
     if not args.tune and not launch:
         from paper_2304_08052_amd import autotune
@@ -274,6 +313,7 @@ def main():
     m_per_src = np.repeat(batch["n_mic"], batch["n_src"]).astype(np.int64)
     taps = int(np.sum(plan.n_img.astype(np.int64) * m_per_src)) * fr.FRAMRIR_TAPS
     out_bytes = info.out_floats * 4
+    path = plan.launch.get("render_path", 0)
 
     table = plan.empty_table()
     out = plan.empty_out()
@@ -297,25 +337,36 @@ def main():
         fwd_step()
         plan.backward(table, grad, ws=ws, prepared=True)
 
+    def events(n):
+        return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+
+    def per_step(fn, n, inner=None):
+        """n steps of fn, each between its own pair of events on the launch
+        stream; returns the per-step times (ms) and the whole span (ms)."""
+        evs = events(n)
+        torch.cuda.synchronize()
+        for k in range(n):
+            evs[k][0].record(stream)
+            fn() if inner is None else fn(inner[k])
+            evs[k][1].record(stream)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in evs]), evs[0][0].elapsed_time(evs[-1][1])
+
+    def pct(a):
+        return [float(np.percentile(a, q)) for q in (10, 50, 90)]
+
     for _ in range(args.warmup):
         fwd_step()
     torch.cuda.synchronize()
 
     # ---- eager forward, with per-launch render events
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for k in range(args.steps):
-        fwd_step(evs[k])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    eager_ms = t_start.elapsed_time(t_end) / args.steps
-    render_each = np.array([a.elapsed_time(b) for a, b in evs])
-    render_ms = float(np.mean(render_each))
+    revs = events(args.steps)
+    eager_each, _ = per_step(fwd_step, args.steps, inner=revs)
+    render_each = np.array([a.elapsed_time(b) for a, b in revs])
+    render_ms = float(np.median(render_each))
 
-    # ---- hipGraph-captured forward step (draw + render)
-    graph_ms = None
+    # ---- hipGraph-captured forward step (draw + render): the headline
+    graph_each = None
     if not args.no_graph:
         try:
             g = torch.cuda.CUDAGraph()
@@ -330,88 +381,73 @@ def main():
             for _ in range(args.warmup):
                 g.replay()
             torch.cuda.synchronize()
-            t_start.record(stream)
-            for _ in range(args.steps):
-                g.replay()
-            t_end.record(stream)
-            torch.cuda.synchronize()
-            graph_ms = t_start.elapsed_time(t_end) / args.steps
+            graph_each, _ = per_step(g.replay, args.steps)
         except Exception as exc:      # graph capture unavailable: report eager only
             print(f"[bench] graph capture failed: {exc}", file=sys.stderr)
-            graph_ms = None
+            graph_each = None
 
-    # ---- forward + backward
-    fb_ms = None
+    # ---- forward + backward (draws held fixed), and through the draws
+    fb_each = fbd_each = None
     if not args.no_backward:
         for _ in range(max(1, args.warmup // 2)):
             bwd_step()
-        torch.cuda.synchronize()
-        t_start.record(stream)
-        for _ in range(args.steps):
-            bwd_step()
-        t_end.record(stream)
-        torch.cuda.synchronize()
-        fb_ms = t_start.elapsed_time(t_end) / args.steps
+        fb_each, _ = per_step(bwd_step, args.steps)
 
-    # ---- forward + backward through the draws (images moving with the inputs)
-    fbd_ms = None
-    if not args.no_backward:
         def bwd_draws_step():
             fwd_step()
             plan.backward_draws(table, grad, ws=ws, prepared=True)
         for _ in range(max(1, args.warmup // 2)):
             bwd_draws_step()
-        torch.cuda.synchronize()
-        t_start.record(stream)
-        for _ in range(args.steps):
-            bwd_draws_step()
-        t_end.record(stream)
-        torch.cuda.synchronize()
-        fbd_ms = t_start.elapsed_time(t_end) / args.steps
+        fbd_each, _ = per_step(bwd_draws_step, args.steps)
 
     early_ms = None
     if args.early:
         early_buf, start_buf = plan.early(out)
-        torch.cuda.synchronize()
-        t_start.record(stream)
-        for _ in range(args.steps):
-            plan.early(out, early=early_buf, start=start_buf)
-        t_end.record(stream)
-        torch.cuda.synchronize()
-        early_ms = t_start.elapsed_time(t_end) / args.steps
+        e_each, _ = per_step(lambda: plan.early(out, early=early_buf, start=start_buf), args.steps)
+        early_ms = float(np.median(e_each))
 
+    # ---- the plain per-room launch path on the same GPU (comparator)
     per_room_ms = None
-    if args.per_room:
-        pr = fr.PerRoom(batch, launch=launch)
+    if not args.no_per_room:
+        pr = fr.PerRoom(batch, launch=plan.launch)
         pr_out = torch.empty_like(out)
-        for _ in range(max(1, args.warmup // 2)):
+        for _ in range(2):
             pr.forward(pr_out)
-        torch.cuda.synchronize()
-        reps = max(1, args.steps // 10)
-        t_start.record(stream)
-        for _ in range(reps):
-            pr.forward(pr_out)
-        t_end.record(stream)
-        torch.cuda.synchronize()
-        per_room_ms = t_start.elapsed_time(t_end) / reps
+        pr_each, _ = per_step(lambda: pr.forward(pr_out), max(2, args.steps // 10))
+        per_room_ms = float(np.median(pr_each))
         fwd_step()
         torch.cuda.synchronize()
         if not torch.equal(pr_out, out):
             raise RuntimeError("per-room path disagrees with the batched path")
 
-    step_ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
+    eager_ms = float(np.median(eager_each))
+    graph_ms = float(np.median(graph_each)) if graph_each is not None else None
+    head_each = graph_each if graph_each is not None else eager_each
+    step_ms = float(np.median(head_each))
+    fb_ms = float(np.median(fb_each)) if fb_each is not None else None
+    fbd_ms = float(np.median(fbd_each)) if fbd_each is not None else None
     value = n_rirs / (step_ms * 1e-3)
     achieved = taps * FLOPS_PER_TAP / (render_ms * 1e-3) / 1e12
     cpu = cpu_baseline(batch, args.cpu_rooms) if args.cpu_rooms > 0 else None
     traffic = measured_traffic(args.workload, plan.launch)
+    step_traffic = measured_step_traffic(args.workload, plan.launch)
     insts = measured_valu_insts(args.workload, plan.launch)
     # a wave64 VALU instruction holds a 16-lane SIMD for 4 clocks: 1,024 SIMDs
     # at 2.4 GHz issue at most 614.4 G wave instructions per second
     valu_issue = insts[0] / (render_ms * 1e-3) / (1024 * 2.4e9 / 4) if insts else None
-    # algorithmic render bytes: every image row (32 B) read once per microphone
+    # secondary byte model: every image row (32 B) read once per microphone
     # group of its source, every output sample (4 B) written once
     groups = np.repeat(-(-batch["n_mic"] // plan.launch["max_mic_group"]), batch["n_src"]).astype(np.int64)
-    algo_bytes = int(np.sum(plan.n_img.astype(np.int64) * groups)) * 32 + out_bytes
+    row_bytes = int(np.sum(plan.n_img.astype(np.int64) * groups)) * 32 + out_bytes
+    mfma = None
+    if path == 1:
+        blocks = int(info.fir_blocks)
+        mflops = blocks * MOMENT_MFMA_PER_BLOCK * 16 * 16 * 32 * 2
+        mfma = {"flops_per_launch": mflops, "tflops": mflops / (render_ms * 1e-3) / 1e12,
+                "peak": FP16_MFMA_PEAK_TFLOPS, "frac": mflops / (render_ms * 1e-3) / 1e12 / FP16_MFMA_PEAK_TFLOPS,
+                "blocks_of_256_samples": blocks}
+    kernel = "render_moment_kernel" if path == 1 else "render_kernel"
+    prof = _profile_path("hbm", plan.launch, HBM_PROFILE)
 
     line = {
         "metric": METRIC,
@@ -421,6 +457,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": step_ms,
+        "ms_per_step_p10_p50_p90": pct(head_each),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -435,38 +472,53 @@ def main():
             "image_rows": int(info.n_img),
             "draws": "FP64 bit-exact",
             "launch": plan.launch,
+            "render_path": "bin moments (matrix-core FIR)" if path == 1 else "scatter",
             "work_items": int(info.n_items),
+            "timed_step": "hipGraph replay of draws + preparation + render" if graph_each is not None
+            else "eager draws + preparation + render",
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "render_kernel",
+            "kernel": kernel,
             "achieved": achieved,
-            "peak": FP32_NONPACKED_PEAK_TFLOPS,
+            "peak": FP32_PUBLISHED_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / FP32_NONPACKED_PEAK_TFLOPS,
-            "frac_of_published_157": achieved / FP32_PUBLISHED_PEAK_TFLOPS,
+            "frac": achieved / FP32_PUBLISHED_PEAK_TFLOPS,
+            "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS,
+            "frac_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS,
+            "peak_nonpacked_derivation": "256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, FP32 without packed "
+                                         "instructions",
             "traffic": traffic,
-            "traffic_source": os.path.relpath(HBM_PROFILE, HERE) if traffic else None,
-            "traffic_over_algorithmic": traffic / algo_bytes if traffic else None,
-            "algorithmic_bytes": algo_bytes,
+            "traffic_source": os.path.relpath(prof, HERE) if traffic else None,
+            "algorithmic_bytes": out_bytes,
+            "traffic_over_algorithmic": traffic / out_bytes if traffic else None,
+            "step_traffic": step_traffic,
+            "step_traffic_over_algorithmic": step_traffic / out_bytes if step_traffic else None,
+            "algorithmic_bytes_with_rows": row_bytes,
             "tap_updates_per_launch": taps,
             "flops_per_tap": FLOPS_PER_TAP,
             "render_ms": render_ms,
-            "render_ms_p10_p50_p90": [float(np.percentile(render_each, q)) for q in (10, 50, 90)],
+            "render_ms_p10_p50_p90": pct(render_each),
             "valu_issue_frac_counters": valu_issue,
             "valu_lds_wave_insts_counters": list(insts) if insts else None,
-            "counters_source": os.path.relpath(VALU_PROFILE, HERE) if insts else None,
+            "counters_source": os.path.relpath(_profile_path("valu", plan.launch, VALU_PROFILE), HERE)
+            if insts else None,
+            "mfma_fp16": mfma,
             "hbm_write_gbs": out_bytes / (render_ms * 1e-3) / 1e9,
             "hbm_frac": out_bytes / (render_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_par,
+        "cpu_baseline_long_filters_all_cores": cpu_long,
         "eager_ms_per_step": eager_ms,
+        "eager_ms_p10_p50_p90": pct(eager_each),
         "graph_ms_per_step": graph_ms,
         "fwd_bwd_ms_per_step": fb_ms,
+        "fwd_bwd_ms_p10_p50_p90": pct(fb_each) if fb_each is not None else None,
         "fwd_bwd_over_fwd": (fb_ms / eager_ms) if fb_ms else None,
         "fwd_bwd_draws_ms_per_step": fbd_ms,
         "per_room_ms_per_step": per_room_ms,
+        "per_room_over_batched": (per_room_ms / step_ms) if per_room_ms else None,
         "early_ms": early_ms,
         "plan_host_ms": plan_ms,
         "autotune_top": tuned,

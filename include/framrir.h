@@ -108,8 +108,16 @@ typedef struct framrir_params {
  *                or 1024,
  * bwd_grid_wgs   workgroups of the persistent backward grid (0 = as many as
  *                fit, capped at the number of items).
+ * render_path    0: the scatter (every pulse tap added to an LDS tile of the
+ *                RIR); 1: bin moments (per pair six moments of its
+ *                fractional delay added to its integer-delay bin plus its five
+ *                centre taps, then the fixed pulse filter over the bins on the
+ *                matrix cores; waves_per_simd must be 4); the results agree
+ *                within FP32 rounding.
  * A time tile holds tile_len = floor(lds_bytes / 4 / m_group) - 160 samples
- * of m_group microphones; rooms whose RIR is longer are split in time.  The
+ * of m_group microphones for the scatter; for the bin moments the largest
+ * tile_len = 256 n (n <= 31) with 28 m_group (R + 4 ceil(R / 32)) <= lds_bytes,
+ * R = tile_len + 80; rooms whose RIR is longer are split in time.  The
  * backward runs over the same work items as the render. */
 typedef struct framrir_launch {
     int32_t lds_bytes;
@@ -119,6 +127,7 @@ typedef struct framrir_launch {
     int32_t waves_per_simd;
     int32_t bwd_wg_threads;
     int32_t bwd_grid_wgs;
+    int32_t render_path;
 } framrir_launch;
 
 /* Sizes of a plan. */
@@ -139,6 +148,7 @@ typedef struct framrir_plan_info {
     int32_t multirate;     /* 1 for a FRAMRIR_FLAG_MULTIRATE plan */
     int64_t mr_floats;     /* multi-rate plans: floats of one intermediate signal at r_l fs */
     int64_t ws_mr_bytes;   /* multi-rate plans: workspace of framrir_forward_multirate */
+    int64_t fir_blocks;    /* render_path 1: 256-sample blocks of the bin-moment filter per render */
 } framrir_plan_info;
 
 typedef struct framrir_plan framrir_plan; /* opaque, host memory */

@@ -975,6 +975,378 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
 }
 
 // ---------------------------------------------------------------------------
+// Render by bin moments (the second render path)
+// ---------------------------------------------------------------------------
+// For the taps |m| >= 3 the pulse is a polynomial in the fractional delay of
+// degree <= 5 (tap_poly.h): A P(m - dl) = S Q_m(dl) = sum_k c_{m,k} 2^-k
+// S (2 dl)^k.  Summed over the pairs whose centre tap falls on sample K (k =
+// K), sample n of a channel receives
+//   h[n] = sum_{|m| >= 3} sum_k (c_{m,k} 2^-k) U_k[n - m] + centre taps,
+//   U_k[K] = sum over those pairs of S (2 dl)^k,
+// so a pair adds its six moments U_0..U_5 to its bin and its five centre taps
+// (m = 0, +-1, +-2, quotient form) to a direct row: 11 LDS atomics instead of
+// 81.  The moments are fixed-point integers under the source's scale
+// ((2 dl)^k <= 1 keeps each inside the budget), added with ds_add_u32, so
+// their sums do not depend on the order of the additions.
+// The sum over m is a fixed banded (Toeplitz) product per power k, done on
+// the matrix cores: a block of 256 output samples of one microphone is a
+// 16 x 16 tile D[i][b] = h[n0 + 16 b + i] = sum_k W_k X_k, with W_k[i][q] =
+// c_{i-q+40,k} 2^-k (zero outside the band and for |m| < 3) and X_k[q][b] =
+// U_k[n0 + 16 b - 40 + q], q in [0, 96).  Operands are fp16: a moment enters
+// as v = U 2^-16 split into hi = fp16(v) and lo = fp16(v - hi), a coefficient
+// likewise, and the FP32 accumulator takes hi*hi + hi*lo + lo*hi (powers 0-2;
+// for powers 3-5, whose terms are at most 2^-9 of the sum, hi*hi), so every
+// term keeps about 22 bits.  Integer bins and a fixed MFMA order make the
+// output bitwise reproducible.
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMomPow = 6;        // moments U_0 .. U_5
+constexpr int kMomSplit = 3;      // powers below this use hi + lo operands
+constexpr int kMomSteps = 13;     // K-steps of 32 over (power, q)
+constexpr int kMomStepPow[kMomSteps] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 4, 5};
+constexpr int kMomStepQ[kMomSteps] = {0, 32, 64, 0, 32, 64, 0, 32, 64, 16, 48, 32, 32};
+constexpr float kMomSigma = 1.0f / 65536.0f;   // |U| < 2^31, so |U 2^-16| < 2^15 fits fp16
+constexpr int kMomGroup = 4;     // 256-sample blocks a wave runs side by side
+
+constexpr float pow2i(int e) {
+    float v = 1.0f;
+    for (; e > 0; --e) v *= 2.0f;
+    for (; e < 0; ++e) v *= 0.5f;
+    return v;
+}
+
+// Every nonzero W_k[i][q] lies in exactly one K-step of its power, every
+// polynomial tap has degree < kMomPow, and the steps stay inside q < 96.
+constexpr bool mom_steps_cover() {
+    for (int m = 3; m <= kHalf; ++m)
+        if (kPolyDeg[kHalf + m] >= kMomPow || kPolyDeg[kHalf - m] >= kMomPow) return false;
+    for (int s = 0; s < kMomSteps; ++s) {
+        if (kMomStepQ[s] < 0 || kMomStepQ[s] + 32 > 2 * kHalf + 16) return false;
+        for (int t = s + 1; t < kMomSteps; ++t)
+            if (kMomStepPow[s] == kMomStepPow[t] && kMomStepQ[s] < kMomStepQ[t] + 32 &&
+                kMomStepQ[t] < kMomStepQ[s] + 32)
+                return false;
+    }
+    for (int k = 0; k < kMomPow; ++k)
+        for (int m = -kHalf; m <= kHalf; ++m) {
+            if ((m > -3 && m < 3) || k > kPolyDeg[kHalf + m]) continue;
+            for (int i = 0; i < 16; ++i) {
+                const int q = i - m + kHalf;
+                bool hit = false;
+                for (int s = 0; s < kMomSteps; ++s)
+                    if (kMomStepPow[s] == k && q >= kMomStepQ[s] && q < kMomStepQ[s] + 32) hit = true;
+                if (!hit) return false;
+            }
+        }
+    return true;
+}
+static_assert(mom_steps_cover(), "the K-steps must cover the band of every power exactly once");
+
+constexpr uint32_t f16_bits(float x) { return __builtin_bit_cast(uint16_t, static_cast<_Float16>(x)); }
+
+// W_k fragments in the MFMA A-operand layout of v_mfma_f32_16x16x32_f16
+// (lane l: row l % 16, columns 8 (l / 16) .. + 7 of the step), hi and lo.
+struct alignas(16) MomFrags {
+    uint32_t w[kMomSteps][2][64][4];
+    constexpr MomFrags() : w{} {
+        for (int s = 0; s < kMomSteps; ++s)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 8; ++e) {
+                    const int k = kMomStepPow[s];
+                    const int i = l % 16, q = kMomStepQ[s] + 8 * (l / 16) + e, m = i - q + kHalf;
+                    float c = 0.0f;
+                    if (m >= -kHalf && m <= kHalf && (m <= -3 || m >= 3) && k <= kPolyDeg[kHalf + m])
+                        c = kPolyCoef[kHalf + m][k] * pow2i(-k);
+                    const float hi = static_cast<float>(static_cast<_Float16>(c));
+                    const float lo = k < kMomSplit ? c - hi : 0.0f;
+                    w[s][0][l][e / 2] |= f16_bits(hi) << (16 * (e & 1));
+                    w[s][1][l][e / 2] |= f16_bits(lo) << (16 * (e & 1));
+                }
+    }
+};
+__device__ constexpr MomFrags kMomFrags{};
+
+__device__ __forceinline__ f32x4 mfma_16x16x32(const u32x4& a, const u32x4& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                  0, 0);
+}
+
+// In-place conversion of the moment rows of an item to fp16 operands, each
+// thread rewriting only the words it reads (no barrier inside):
+//   rows 0 .. kMomSplit-1, bins (2p, 2p+1) in words (2p, 2p+1) become
+//     word 2p = hi halves of both bins, word 2p+1 = lo halves;
+//   the other rows, bins 4p .. 4p+3 in words 4p .. 4p+3 become
+//     words 4p, 4p+1 = hi halves of the four bins (4p+2, 4p+3 unused).
+// Bin e's hi half thus sits in word e & ~1 (split rows) or (e & ~3) + (e & 3)/2
+// (hi-only rows), low or high half by e & 1.
+__device__ __forceinline__ uint32_t pack_f16(float a, float b) {
+    return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<_Float16>(a))) |
+           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<_Float16>(b))) << 16);
+}
+
+__device__ __forceinline__ float f16_lo_of(uint32_t w) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w & 0xffffu)));
+}
+
+__device__ __forceinline__ float f16_hi_of(uint32_t w) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w >> 16)));
+}
+
+__device__ __forceinline__ int mom_word(int e) { return e + 4 * (e >> 5); }
+
+template <int NT>
+__device__ __forceinline__ void mom_convert(int* __restrict__ lds, int mg, int Rw, int tid) {
+    // the rows are converted whole, pad words included (they hold zeros)
+    for (int m = 0; m < mg; ++m) {
+        int* base = lds + m * (kMomRows * Rw);
+        // split rows: kMomSplit Rw words as pairs
+        int2* sp = reinterpret_cast<int2*>(base);
+        for (int p = tid; p < (kMomSplit * Rw) / 2; p += NT) {
+            const int2 u = sp[p];
+            const float a = static_cast<float>(u.x) * kMomSigma, b = static_cast<float>(u.y) * kMomSigma;
+            const uint32_t hw = pack_f16(a, b);
+            const uint32_t lw = pack_f16(a - f16_lo_of(hw), b - f16_hi_of(hw));
+            sp[p] = make_int2(static_cast<int>(hw), static_cast<int>(lw));
+        }
+        // hi-only rows: (kMomPow - kMomSplit) Rw words as quads
+        i32x4* qp = reinterpret_cast<i32x4*>(base + kMomSplit * Rw);
+        for (int p = tid; p < ((kMomPow - kMomSplit) * Rw) / 4; p += NT) {
+            const i32x4 u = qp[p];
+            const uint32_t h0 = pack_f16(static_cast<float>(u[0]) * kMomSigma, static_cast<float>(u[1]) * kMomSigma);
+            const uint32_t h1 = pack_f16(static_cast<float>(u[2]) * kMomSigma, static_cast<float>(u[3]) * kMomSigma);
+            *reinterpret_cast<int2*>(qp + p) = make_int2(static_cast<int>(h0), static_cast<int>(h1));
+        }
+    }
+}
+
+// The rows of an item's tile and a thread's walk over its pairs (p = m
+// n_list + e, row j = e P mod n_list with P prime, coprime to n_list, so that
+// the lanes of a wave take rows spread over the delay range); the first row
+// is loaded on set-up, so that it can be issued an item ahead.
+struct MomWalk {
+    const double4* rows;
+    int n_list, n_pairs, jstep, m, e, j, p;
+    double4 row;
+};
+
+template <int NT>
+__device__ __forceinline__ void mom_walk_init(MomWalk& w, const ItemCtx& c, const int* __restrict__ bucket_off,
+                                              const double* __restrict__ sorted, int tid) {
+    int lo = 0, hi = c.n_img;
+    if (!c.w.full) {
+        const float inv_w = bucket_inv_width(c.T);
+        const int b_lo = bucket_of(c.w.t0 - c.margin - 41.0f, inv_w);
+        const int b_hi = bucket_of((c.w.t0 + c.w.len + c.margin + 41.0f), inv_w);
+        const int* bo = bucket_off + static_cast<int64_t>(c.w.src) * (kBuckets + 1);
+        lo = bo[b_lo];
+        hi = bo[b_hi + 1];
+    }
+    w.rows = reinterpret_cast<const double4*>(sorted) + c.img_off + lo;
+    w.n_list = hi - lo;
+    int P = 97;
+    while (w.n_list > 0 && w.n_list % P == 0) P = (P == 97) ? 89 : 83;
+    w.jstep = w.n_list > 0 ? static_cast<int>((static_cast<int64_t>(NT) * P) % w.n_list) : 0;
+    w.n_pairs = w.n_list * c.w.n_mic;
+    w.m = 0;
+    w.e = tid;
+    while (w.e >= w.n_list && w.m < c.w.n_mic) {
+        w.e -= w.n_list;
+        ++w.m;
+    }
+    w.j = w.n_list > 0 ? static_cast<int>((static_cast<int64_t>(w.e) * P) % w.n_list) : 0;
+    w.p = tid;
+    w.row = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (tid < w.n_pairs) w.row = w.rows[w.j];
+}
+
+template <int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
+render_moment_kernel(const void* __restrict__ desc, const double* __restrict__ mic, const double* __restrict__ r_in,
+                     float* __restrict__ out, int* __restrict__ counters, const float* __restrict__ src_scale,
+                     const int* __restrict__ bucket_off, const double* __restrict__ sorted, int lds_words) {
+    extern __shared__ u32x4 lds_v[];
+    int* lds = reinterpret_cast<int*>(lds_v);
+    __shared__ double micq[3 * kMaxMicGroup];
+    __shared__ int s_item;
+    const DescHeader* H = hdr(desc);
+    const int n_items = H->n_items;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = NT / 64;
+    // bins start at zero; each item clears what it used
+    for (int k = tid; k < (lds_words >> 2); k += NT) lds_v[k] = u32x4{0u, 0u, 0u, 0u};
+    if (tid == 0) s_item = atomicAdd(&counters[0], 1);
+    __syncthreads();
+    int item = __builtin_amdgcn_readfirstlane(s_item);
+    // The items run as a pipeline: the next item's queue slot is taken while
+    // this one's bins are converted, and its descriptor, microphone positions
+    // and first rows load while this one's filter runs on the matrix cores.
+    ItemCtx c;
+    MomWalk wk;
+    if (item < n_items) {
+        load_item(desc, item, mic, r_in, c);
+        if (tid < 3 * c.w.n_mic) micq[tid] = mic[3 * c.mic0_glob + tid];
+        mom_walk_init<NT>(wk, c, bucket_off, sorted, tid);
+    }
+    __syncthreads();
+    while (item < n_items) {
+        const int mg = c.w.n_mic;
+        const int nblk = (c.w.len + kMomBlock - 1) / kMomBlock;
+        const int R = nblk * kMomBlock + 2 * kHalf;   // bins t0 - 40 .. t0 + 256 nblk + 39
+        const int Rw = mom_row_words(R);              // words of a row, pads included
+        const int mic_words = kMomRows * Rw;
+        const float scale = src_scale[c.w.src];
+        // ---- scatter: per pair (row, microphone) six moments and five centre taps
+        for (; wk.p < wk.n_pairs; wk.p += NT) {
+            const double4 cur = wk.row;
+            const int mc = wk.m;
+            wk.e += NT;
+            wk.j += wk.jstep;
+            if (wk.j >= wk.n_list) wk.j -= wk.n_list;
+            while (wk.e >= wk.n_list && wk.m < mg) {
+                wk.e -= wk.n_list;
+                ++wk.m;
+            }
+            if (wk.p + NT < wk.n_pairs) wk.row = wk.rows[wk.j];   // the next pair's row loads during this one
+            const double* q = micq + 3 * mc;
+            const Pair Pp = c.hr > 0.0 ? pair_setup_high_rate(cur.x, cur.y, cur.z, q[0], q[1], q[2], c.c0, c.hr,
+                                                              c.lm1, c.rl, c.rh, render_row_amp(cur.w))
+                                       : pair_setup(cur.x, cur.y, cur.z, q[0], q[1], q[2], c.fs_over_c,
+                                                    render_row_amp(cur.w));
+            const int bin = Pp.k - c.w.t0 + kHalf;
+            if (bin < 0 || bin >= R) continue;
+            int* base = lds + mc * mic_words;
+            const float as = (Pp.A * scale) * Pp.sinc;   // A scale sinc(dl)
+            const float S = as * Pp.dl;                    // A scale sin(pi dl) / pi
+            const float x2 = Pp.dl + Pp.dl;
+            const int wb = mom_word(bin);
+            float mk = S;
+#pragma unroll
+            for (int k = 0; k < kMomPow; ++k) {
+                atomicAdd(base + k * Rw + wb, cvt_rpi_i32(mk));
+                mk *= x2;
+            }
+            int* dr = base + kMomPow * Rw;
+            atomicAdd(dr + wb, cvt_rpi_i32(as * (Pp.cy * Pp.cy)));
+            if (bin >= 1) atomicAdd(dr + mom_word(bin - 1), cvt_rpi_i32(tap_quotient<-1>(Pp.dl, S, Pp.cy, Pp.sy)));
+            if (bin >= 2) atomicAdd(dr + mom_word(bin - 2), cvt_rpi_i32(tap_quotient<-2>(Pp.dl, S, Pp.cy, Pp.sy)));
+            if (bin + 1 < R) atomicAdd(dr + mom_word(bin + 1), cvt_rpi_i32(tap_quotient<1>(Pp.dl, S, Pp.cy, Pp.sy)));
+            if (bin + 2 < R) atomicAdd(dr + mom_word(bin + 2), cvt_rpi_i32(tap_quotient<2>(Pp.dl, S, Pp.cy, Pp.sy)));
+        }
+        __syncthreads();
+        // ---- the next item's slot; moments to fp16 operands (in place)
+        if (tid == 0) s_item = atomicAdd(&counters[0], 1);
+        mom_convert<NT>(lds, mg, Rw, tid);
+        __syncthreads();
+        const int next = __builtin_amdgcn_readfirstlane(s_item);
+        ItemCtx cn;
+        MomWalk wn;
+        if (next < n_items) {   // its loads are in flight during the filter
+            load_item(desc, next, mic, r_in, cn);
+            mom_walk_init<NT>(wn, cn, bucket_off, sorted, tid);
+        }
+        // ---- FIR on the matrix cores: a wave takes kMomGroup blocks of 256
+        // samples side by side (independent accumulators); the coefficient
+        // fragments come through a three-deep register ring, two steps ahead
+        const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
+        const float inv_mom = inv * (1.0f / kMomSigma);
+        const int col = lane & 15, grp = lane >> 4;
+        const int end = min(c.w.t0 + c.w.len, c.T);
+        const int nb = mg * nblk;
+        for (int g0 = wave; g0 < nb; g0 += NW * kMomGroup) {
+            f32x4 acc[kMomGroup];
+            int eo0[kMomGroup], mo0[kMomGroup];
+#pragma unroll
+            for (int i = 0; i < kMomGroup; ++i) {
+                acc[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                const int blk = g0 + NW * i, mm = blk / nblk, beta = blk - mm * nblk;
+                // bin of the lane's first operand at q = 0, and its microphone's rows
+                eo0[i] = beta * kMomBlock + 16 * col + 8 * grp;
+                mo0[i] = mm * mic_words;
+            }
+            // the lane index made opaque, so that the fragment loads stay in
+            // the loop (registers) instead of being hoisted for the whole item
+            int fl = lane;
+            asm volatile("" : "+v"(fl));
+            u32x4 fh[3], fo[3];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                fh[s] = *reinterpret_cast<const u32x4*>(kMomFrags.w[s][0][fl]);
+                fo[s] = *reinterpret_cast<const u32x4*>(kMomFrags.w[s][1][fl]);
+            }
+#pragma unroll
+            for (int s = 0; s < kMomSteps; ++s) {
+                const int k = kMomStepPow[s];
+                if (s + 2 < kMomSteps) {
+                    fh[(s + 2) % 3] = *reinterpret_cast<const u32x4*>(kMomFrags.w[s + 2][0][fl]);
+                    if (kMomStepPow[s + 2] < kMomSplit)
+                        fo[(s + 2) % 3] = *reinterpret_cast<const u32x4*>(kMomFrags.w[s + 2][1][fl]);
+                }
+                const u32x4 ah = fh[s % 3], al = fo[s % 3];
+#pragma unroll
+                for (int i = 0; i < kMomGroup; ++i) {
+                    if (g0 + NW * i >= nb) break;   // wave-uniform
+                    // the 8 bins e .. e + 7 of the operand (e a multiple of 8:
+                    // consecutive words inside one 32-bin run)
+                    const int* w = lds + mo0[i] + k * Rw + mom_word(eo0[i] + kMomStepQ[s]);
+                    if (k < kMomSplit) {
+                        const u32x4 w0 = *reinterpret_cast<const u32x4*>(w);
+                        const u32x4 w1 = *reinterpret_cast<const u32x4*>(w + 4);
+                        const u32x4 bh = u32x4{w0[0], w0[2], w1[0], w1[2]};
+                        const u32x4 bl = u32x4{w0[1], w0[3], w1[1], w1[3]};
+                        acc[i] = mfma_16x16x32(ah, bh, acc[i]);
+                        acc[i] = mfma_16x16x32(ah, bl, acc[i]);
+                        acc[i] = mfma_16x16x32(al, bh, acc[i]);
+                    } else {
+                        const uint2 w0 = *reinterpret_cast<const uint2*>(w);
+                        const uint2 w1 = *reinterpret_cast<const uint2*>(w + 4);
+                        acc[i] = mfma_16x16x32(ah, u32x4{w0.x, w0.y, w1.x, w1.y}, acc[i]);
+                    }
+                }
+                // one step's operands in flight at a time (bounds the registers)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // lane: samples n .. n + 3 (rows 4 grp .. 4 grp + 3 of column col)
+#pragma unroll
+            for (int i = 0; i < kMomGroup; ++i) {
+                const int blk = g0 + NW * i;
+                if (blk >= nb) break;
+                const int mm = blk / nblk, beta = blk - mm * nblk;
+                const int off = beta * kMomBlock + 16 * col + 4 * grp;
+                const int n = c.w.t0 + off;
+                const i32x4 d =
+                    *reinterpret_cast<const i32x4*>(lds + mm * mic_words + kMomPow * Rw + mom_word(off + kHalf));
+                float* dst =
+                    out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + mm) * c.T;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (n + r < end) dst[n + r] = __builtin_fmaf(acc[i][r], inv_mom, static_cast<float>(d[r]) * inv);
+            }
+        }
+        __syncthreads();
+        // clear this item's rows; the next item's microphones
+        for (int k = tid; k < (mg * mic_words) >> 2; k += NT) lds_v[k] = u32x4{0u, 0u, 0u, 0u};
+        if (next < n_items && tid < 3 * cn.w.n_mic) micq[tid] = mic[3 * cn.mic0_glob + tid];
+        __syncthreads();
+        item = next;
+        c = cn;
+        wk = wn;
+    }
+    // the last workgroup to finish rewinds the queue for the next launch
+    if (tid == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counters[1], 1);
+        if (done == static_cast<int>(gridDim.x) - 1) {
+            atomicExch(&counters[0], 0);
+            atomicExch(&counters[1], 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
 // Sums the partials of room b's items in the plan's fixed order (room_items)
@@ -1736,6 +2108,22 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
     const int acc_words = plan->launch.lds_bytes / 4;
     const dim3 grid(plan->grid), block(plan->launch.wg_threads);
     const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
+    if (plan->launch.render_path == 1) {   // compiled at 4 waves per SIMD only (the plan checks it)
+        switch (key) {
+#define FR_CASE(NT)                                                                                         \
+    case NT * 16 + 4:                                                                                       \
+        if (int rc = allow_lds<render_moment_kernel<NT, 4>, kLdsPerCu - kMomStaticLds>()) return rc;        \
+        hipLaunchKernelGGL((render_moment_kernel<NT, 4>), grid, block, lds, st, desc_dev, mic_dev, r_dev,   \
+                           out_dev, w.counters, w.src_scale, w.bucket_off, w.sorted, acc_words);            \
+        break;
+            FR_CASE(256) FR_CASE(512) FR_CASE(1024)
+#undef FR_CASE
+            default:
+                return fr_fail(FRAMRIR_E_UNSUPPORTED, "launch shape %d threads x %d waves/SIMD not compiled",
+                               plan->launch.wg_threads, plan->launch.waves_per_simd);
+        }
+        return check_launch("render_moment_kernel");
+    }
     switch (key) {
 #define FR_CASE(NT, WPE)                                                                                    \
     case NT * 16 + WPE:                                                                                     \

@@ -102,7 +102,7 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     } else {
         prm = framrir_params{0.25, 1.0, -2.0, 2.0, 0.25, 1024, 4096, FRAMRIR_TAPS, 0u};
     }
-    framrir_launch launch = launch_in ? *launch_in : framrir_launch{131072, 1024, 0, 8, 4, 0, 0};
+    framrir_launch launch = launch_in ? *launch_in : framrir_launch{131072, 1024, 0, 8, 4, 0, 0, 0};
     if (launch.max_mic_group == 0) launch.max_mic_group = 8;
     if (launch.waves_per_simd == 0) launch.waves_per_simd = 4;
     if (launch.bwd_wg_threads == 0) launch.bwd_wg_threads = launch.wg_threads;
@@ -137,9 +137,10 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "waves_per_simd must be 4 or 8 (got %d)", launch.waves_per_simd);
     if (launch.wg_threads != 256 && launch.wg_threads != 512 && launch.wg_threads != 1024)
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "wg_threads must be 256, 512 or 1024 (got %d)", launch.wg_threads);
-    if (launch.lds_bytes + render_static_lds(launch.wg_threads) > kLdsPerCu)
+    const int render_static = launch.render_path == 1 ? kMomStaticLds : render_static_lds(launch.wg_threads);
+    if (launch.lds_bytes + render_static > kLdsPerCu)
         return fr_fail(FRAMRIR_E_RANGE, "lds_bytes + the render's static LDS (%d) must not exceed %d (got %d)",
-                       render_static_lds(launch.wg_threads), kLdsPerCu, launch.lds_bytes);
+                       render_static, kLdsPerCu, launch.lds_bytes);
     if (launch.bwd_wg_threads != 256 && launch.bwd_wg_threads != 512 && launch.bwd_wg_threads != 1024)
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "bwd_wg_threads must be 0, 256, 512 or 1024 (got %d)",
                        launch.bwd_wg_threads);
@@ -149,6 +150,12 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         return fr_fail(FRAMRIR_E_RANGE, "max_mic_group must be in [1, %d]", kMaxMicGroup);
     if (launch.grid_wgs < 0 || launch.bwd_grid_wgs < 0)
         return fr_fail(FRAMRIR_E_RANGE, "grid_wgs and bwd_grid_wgs must be >= 0");
+    if (launch.render_path != 0 && launch.render_path != 1)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "render_path must be 0 (scatter) or 1 (bin moments) (got %d)",
+                       launch.render_path);
+    if (launch.render_path == 1 && launch.waves_per_simd != 4)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "the bin-moment render runs at 4 waves per SIMD (its matrix-core "
+                                              "FIR needs more than 64 registers)");
 
     framrir_plan* plan = new (std::nothrow) framrir_plan();
     if (!plan) return fr_fail(FRAMRIR_E_INVALID_ARG, "out of host memory");
@@ -382,7 +389,8 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
             const int m0 = (R.n_mic * g) / n_groups;
             const int m1 = (R.n_mic * (g + 1)) / n_groups;
             const int mg = m1 - m0;
-            const int cap = launch.lds_bytes / 4 / mg - 2 * kHalo;
+            const int cap = launch.render_path == 1 ? moment_tile_cap(launch.lds_bytes, mg)
+                                                    : launch.lds_bytes / 4 / mg - 2 * kHalo;
             if (cap < 64) {
                 delete plan;
                 return fr_fail(FRAMRIR_E_RANGE, "lds_bytes %d too small for %d microphones", launch.lds_bytes, mg);
@@ -499,7 +507,8 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
         multirate ? align(plan->ws_taps_off + static_cast<int64_t>(sizeof(float)) * kDecTapStride * n_rooms) : 0;
     int32_t grid = launch.grid_wgs;
     if (grid == 0) {
-        const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + render_static_lds(launch.wg_threads));
+        const int static_lds = launch.render_path == 1 ? kMomStaticLds : render_static_lds(launch.wg_threads);
+        const int per_cu_lds = kLdsPerCu / (launch.lds_bytes + static_lds);
         const int per_cu_waves = launch.waves_per_simd * 4 / (launch.wg_threads / 64);
         const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
         grid = static_cast<int32_t>(std::min<int64_t>(static_cast<int64_t>(it.size()), int64_t(256) * per_cu));
@@ -536,6 +545,11 @@ extern "C" int framrir_plan_get_info(const framrir_plan* plan, framrir_plan_info
     info->multirate = H.multirate;
     info->mr_floats = H.mr_floats;
     info->ws_mr_bytes = plan->ws_mr_bytes;
+    int64_t blocks = 0;
+    if (plan->launch.render_path == 1)
+        for (const framrir::WorkItem& w : plan->items)
+            blocks += static_cast<int64_t>(w.n_mic) * ((w.len + kMomBlock - 1) / kMomBlock);
+    info->fir_blocks = blocks;
     info->n_chan = H.n_chan;
     info->early_floats = H.early_floats;
     return FRAMRIR_OK;

@@ -19,6 +19,28 @@ constexpr int kMaxDynLdsBytes = 160000;
 // Workspace header: work-queue and completion counters of the persistent grid.
 constexpr int64_t kWsCounterBytes = 256;
 
+// Render by bin moments (render_path 1): per microphone 7 rows (six moments
+// and the direct row of the centre taps) of R = 256 nblk + 80 bins for a tile
+// of at most 256 nblk samples.  Bin e sits in word e + 4 (e / 32) of its row
+// (4 pad words after every 32 bins, so that the 16 columns of a matrix-core
+// operand read, 16 bins apart, fall on distinct LDS banks); a row takes
+// mom_row_words(R) words.  Static LDS of that kernel: mic positions and the
+// item slot.
+constexpr int kMomRows = 7;
+constexpr int kMomBlock = 256;
+constexpr int kMomMaxBlocks = 31;   // tiles of at most 7936 samples
+constexpr int kMomStaticLds = 1024;
+constexpr int mom_row_words(int r) { return r + 4 * ((r + 31) / 32); }
+// Longest tile of a group of mg microphones within lds_bytes (a multiple of
+// 256 samples), or 0 when not even one block fits.
+constexpr int moment_tile_cap(int lds_bytes, int mg) {
+    int nblk = 0;
+    while (nblk < kMomMaxBlocks &&
+           static_cast<int64_t>(4) * kMomRows * mg * mom_row_words((nblk + 1) * kMomBlock + 80) <= lds_bytes)
+        ++nblk;
+    return nblk * kMomBlock;
+}
+
 struct framrir_plan {
     framrir_params prm;
     framrir_launch launch;

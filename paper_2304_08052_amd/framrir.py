@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("lds_bytes", ctypes.c_int32), ("wg_threads", ctypes.c_int32), ("grid_wgs", ctypes.c_int32),
                 ("max_mic_group", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("bwd_wg_threads", ctypes.c_int32), ("bwd_grid_wgs", ctypes.c_int32)]
+                ("bwd_wg_threads", ctypes.c_int32), ("bwd_grid_wgs", ctypes.c_int32), ("render_path", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -48,12 +48,13 @@ class PlanInfo(ctypes.Structure):
                 ("desc_bytes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64), ("ws_bwd_bytes", ctypes.c_int64),
                 ("max_T", ctypes.c_int32), ("max_img", ctypes.c_int32), ("early_floats", ctypes.c_int64),
                 ("n_chan", ctypes.c_int32), ("multirate", ctypes.c_int32), ("mr_floats", ctypes.c_int64),
-                ("ws_mr_bytes", ctypes.c_int64)]
+                ("ws_mr_bytes", ctypes.c_int64), ("fir_blocks", ctypes.c_int64)]
 
 
 DEFAULT_PARAMS = dict(alpha=0.25, beta=1.0, a=-2.0, b=2.0, tau=0.25, img_lo=1024, img_hi=4096)
 DEFAULT_LAUNCH = dict(lds_bytes=131072, wg_threads=1024, grid_wgs=0, max_mic_group=8, waves_per_simd=4,
-                      bwd_wg_threads=0, bwd_grid_wgs=0)
+                      bwd_wg_threads=0, bwd_grid_wgs=0, render_path=0)
+RENDER_SCATTER, RENDER_MOMENTS = 0, 1
 
 EXPORTS = {
     "framrir_plan_create": (ctypes.c_int, [ctypes.POINTER(Room), ctypes.c_int32, ctypes.POINTER(Params),
@@ -167,7 +168,7 @@ class Plan:
         p = Params(prm["alpha"], prm["beta"], prm["a"], prm["b"], prm["tau"], prm["img_lo"], prm["img_hi"],
                    FRAMRIR_TAPS, FRAMRIR_FLAG_MULTIRATE if multirate else 0)
         la = Launch(lau["lds_bytes"], lau["wg_threads"], lau["grid_wgs"], lau["max_mic_group"],
-                    lau["waves_per_simd"], lau["bwd_wg_threads"], lau["bwd_grid_wgs"])
+                    lau["waves_per_simd"], lau["bwd_wg_threads"], lau["bwd_grid_wgs"], lau["render_path"])
         handle = ctypes.c_void_p()
         _check(L.framrir_plan_create(rooms, n, ctypes.byref(p), ctypes.byref(la), _np_ptr(self.src),
                                      _np_ptr(self.mic), ctypes.byref(handle)))

@@ -44,7 +44,8 @@ def _setup(n_rooms, launch=None, params=None):
 
 
 @pytest.mark.parametrize("launch", [None, dict(lds_bytes=32768, wg_threads=1024, max_mic_group=2),
-                                    dict(lds_bytes=65536, wg_threads=512, bwd_wg_threads=1024, bwd_grid_wgs=300)])
+                                    dict(lds_bytes=65536, wg_threads=512, bwd_wg_threads=1024, bwd_grid_wgs=300),
+                                    dict(lds_bytes=65536, wg_threads=512, max_mic_group=2, render_path=1)])
 def test_backward_matches_oracle_adjoint(launch):
     torch, fr, batch, plan, table, rooms, oplans, G, _ = _setup(4, launch)
     say(f"backward vs oracle adjoint launch={launch}")

@@ -65,7 +65,9 @@ def _check_draws(plan, table, rooms, oplans):
 
 
 @pytest.mark.parametrize("launch", [None, dict(max_mic_group=16),
-                                    dict(lds_bytes=8192, wg_threads=256, max_mic_group=3)])
+                                    dict(lds_bytes=8192, wg_threads=256, max_mic_group=3),
+                                    dict(lds_bytes=131072, wg_threads=1024, max_mic_group=2, render_path=1),
+                                    dict(lds_bytes=65536, wg_threads=512, max_mic_group=1, render_path=1)])
 def test_edge_rooms_forward(launch):
     batch = W.edge_cases()
     say(f"edge rooms forward launch={launch}")

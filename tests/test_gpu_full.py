@@ -82,13 +82,17 @@ def check_jobs(pool, jobs, label):
         f"median {np.median(chans):.2e}; gradients worst {bwd_worst[0]:.2e} (room {bwd_worst[1]})")
 
 
-def run_batched(batch, seed):
+# the bin-moment render (matrix-core filter) on the same workload
+MOMENTS = dict(lds_bytes=65536, wg_threads=512, grid_wgs=0, max_mic_group=2, waves_per_simd=4, render_path=1)
+
+
+def run_batched(batch, seed, launch=None):
     """The benchmark's forward (prepare with the draws, then render) and the
-    adjoint on that preparation, in the tuned launch shape."""
+    adjoint on that preparation, in the tuned launch shape (or `launch`)."""
     import torch
     from paper_2304_08052_amd import autotune
     from paper_2304_08052_amd import framrir as fr
-    plan = fr.Plan(batch, launch=autotune.launch_for(batch))
+    plan = fr.Plan(batch, launch=launch or autotune.launch_for(batch))
     table, out, ws = plan.empty_table(), plan.empty_out(), plan.workspace(backward=True)
     plan.prepare(table, ws=ws, draw=True)
     plan.render_prepared(table, out=out, ws=ws)
@@ -98,11 +102,12 @@ def run_batched(batch, seed):
     return plan, out, G, gm, gs, gr
 
 
-@pytest.mark.parametrize("which", ["batched256", "long64"])
+@pytest.mark.parametrize("which", ["batched256", "long64", "batched256_moments"])
 def test_every_room_forward_backward(which, oracle_pool):
-    batch = W.config2() if which == "batched256" else W.config3()
-    say(f"{which}: forward + backward of every room in the tuned launch shape")
-    plan, out, G, gm, gs, gr = run_batched(batch, seed=11)
+    batch = W.config3() if which == "long64" else W.config2()
+    launch = MOMENTS if which.endswith("moments") else None
+    say(f"{which}: forward + backward of every room, launch {launch or 'tuned'}")
+    plan, out, G, gm, gs, gr = run_batched(batch, seed=11, launch=launch)
     rooms = range(plan.n_rooms)
     check_jobs(oracle_pool, jobs_for(batch, plan, rooms, out, G, gm, gs, gr), which)
 

@@ -166,7 +166,12 @@ def test_integer_delay_exact_impulse():
 
 @pytest.mark.parametrize("launch", [None, dict(lds_bytes=32768, wg_threads=1024, max_mic_group=3),
                                     dict(lds_bytes=16384, wg_threads=256, max_mic_group=2),
-                                    dict(lds_bytes=65536, wg_threads=512, max_mic_group=8, grid_wgs=7)])
+                                    dict(lds_bytes=65536, wg_threads=512, max_mic_group=8, grid_wgs=7),
+                                    # bin moments: time-tiled 256-sample blocks, groups of 1-3 microphones
+                                    dict(lds_bytes=65536, wg_threads=512, max_mic_group=1, render_path=1),
+                                    dict(lds_bytes=131072, wg_threads=1024, max_mic_group=3, render_path=1),
+                                    dict(lds_bytes=24576, wg_threads=256, max_mic_group=2, grid_wgs=5,
+                                         render_path=1)])
 def test_render_small_mixed_tiles(launch):
     torch, fr = _torch(), _fr()
     say(f"render small_mixed launch={launch}")
