@@ -302,9 +302,9 @@ def main():
         launch = autotune.launch_for(batch)
     if args.tune:
         from paper_2304_08052_amd import autotune
-        best, results = autotune.tune(batch)
+        best, best_ms = autotune.tune(batch)
         launch = dict(best, **launch)
-        tuned = [dict(ms=round(ms, 4), **l) for ms, l in results[:5]]
+        tuned = dict(ms=round(best_ms, 4), **best)
     t0 = time.perf_counter()
     plan = fr.Plan(batch, launch=launch)
     plan_ms = (time.perf_counter() - t0) * 1e3

@@ -409,6 +409,60 @@ int framrir_host_cbrt_rn(const double* x, double* y, int64_t n);
 int framrir_host_sqrt_rn(const double* x, double* y, int64_t n);
 int framrir_host_philox4x32(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n);
 
+/* ---- Handle and launch-shape tuner.  None of this is in the paper: the
+ * launch shape only decides how the batch of the problem of Sec. II (rooms,
+ * T60, positions, fs, c0 -> RIRs [B][S][M][T]) is split over the GPU, never
+ * what is computed.
+ *
+ * framrir_handle_create: a handle for device `device` (host call; the
+ * device's HIP runtime state is initialised).  Errors: INVALID_ARG (no such
+ * device), UNSUPPORTED when the device is not a gfx950 (the kernels are
+ * built for it alone), DEVICE.  It looks up the device address of the static
+ * scratch of framrir_forward_noalloc for that device, and loads the tuning
+ * caches: tune_cache_paths (may be NULL) holds file paths separated by ':';
+ * the first is the cache framrir_tune writes (it need not exist yet; "" for
+ * none), the others read-only fallbacks; entries of earlier paths take
+ * precedence.  Cache file: a JSON object mapping "arch|size class" to
+ * {"launch": {field: integer, ...}, "ms": median milliseconds}.
+ * framrir_handle_destroy frees the handle (the caches stay on disk). */
+typedef struct framrir_handle framrir_handle;
+int framrir_handle_create(int32_t device, const char* tune_cache_paths, framrir_handle** out);
+void framrir_handle_destroy(framrir_handle* h);
+
+/* 1 if a device whose HIP gcnArchName is the given string runs this
+ * library (gfx950, with or without feature suffixes), else 0.  Host only. */
+int framrir_arch_supported(const char* gcn_arch_name);
+
+/* The size class of a batch, the key of the tuning caches (host only):
+ * "fs=F1/F2...;mics<=M;T=lo-hi" with the distinct sample rates (integer Hz,
+ * ascending), the largest microphone count, and the powers of two that
+ * bracket T = ceil(T60 fs) over the rooms.  buf receives it NUL-terminated.
+ * Errors: INVALID_ARG, RANGE, WORKSPACE (buf too short). */
+int framrir_size_class(const framrir_room* rooms, int32_t n_rooms, char* buf, size_t n);
+
+/* Times framrir_forward (draws, preparation and render) of the given batch
+ * under each candidate launch shape on the handle's device (median of reps
+ * runs after two warm-up runs, HIP events on a stream of its own) and keeps
+ * the fastest as the class's entry: in the handle and, when the handle has a
+ * writable cache, in that file (other entries kept).  size_class: the key
+ * (NULL = framrir_size_class of the rooms).  candidates: n_candidates shapes,
+ * or NULL / 0 for the library's search: the scatter (render_path 0) over LDS
+ * tiles, workgroup sizes, register budgets, microphone groups and grid sizes,
+ * and the bin moments (render_path 1) at several tiles.  Shapes that are not
+ * valid for the batch are skipped.  A set-up call: it allocates and frees
+ * device memory and synchronises; never call it under graph capture.  best
+ * and best_ms (may be NULL) receive the winner.  Errors: INVALID_ARG, RANGE
+ * (no valid candidate), DEVICE, and those of framrir_plan_create. */
+int framrir_tune(framrir_handle* h, const framrir_room* rooms, int32_t n_rooms, const framrir_params* prm,
+                 const double* src, const double* mic, const char* size_class, const framrir_launch* candidates,
+                 int32_t n_candidates, int32_t reps, framrir_launch* best, double* best_ms);
+
+/* The cached launch shape of a size class on the handle's architecture:
+ * *found = 1 and *out the entry, or *found = 0 and *out the default shape
+ * (lds 131072, 1024 threads, 8 microphones per item, 4 waves per SIMD,
+ * scatter).  Host only.  Errors: INVALID_ARG. */
+int framrir_tune_lookup(const framrir_handle* h, const char* size_class, framrir_launch* out, int32_t* found);
+
 /* Message for the last error on the calling thread (NUL-terminated, may be
  * truncated to n bytes).  Returns the length of the full message. */
 int framrir_last_error_detail(char* buf, size_t n);

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libframrir.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plan.cpp", "kernels.hip", "spatial.hip"]
+SOURCES = ["plan.cpp", "tune.cpp", "kernels.hip", "spatial.hip"]
 
 # -ffp-contract=off: the draw-stage FP64 arithmetic must round every operation
 # separately.  Packed FP32 instructions are disabled for all GPU code.

@@ -2236,6 +2236,20 @@ int current_scratch(void** out) {
 
 }  // namespace
 
+// Looks up (once) the static scratch of `device`, with that device current;
+// called when a handle is created for the device.
+int framrir_scratch_setup(int device) {
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return fr_fail(FRAMRIR_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if ((e = hipSetDevice(device)) != hipSuccess)
+        return fr_fail(FRAMRIR_E_DEVICE, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
+    void* p = nullptr;
+    const int rc = current_scratch(&p);
+    (void)hipSetDevice(prev);
+    return rc;
+}
+
 extern "C" int framrir_forward_noalloc(const framrir_plan* plan, const void* desc_dev, double* table_dev,
                                        const double* mic_dev, const double* src_dev, const double* r_dev,
                                        float* out_dev, void* stream) {

@@ -92,6 +92,16 @@ EXPORTS = {
     "framrir_last_error_detail": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
     "framrir_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "framrir_version": (ctypes.c_int, []),
+    "framrir_arch_supported": (ctypes.c_int, [ctypes.c_char_p]),
+    "framrir_handle_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "framrir_handle_destroy": (None, [ctypes.c_void_p]),
+    "framrir_size_class": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
+    "framrir_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_double)]),
+    "framrir_tune_lookup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None
@@ -136,6 +146,98 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def room_structs(batch):
+    """The batch as the C ABI takes it: (framrir_room array, n_rooms, src
+    [sum n_src, 3] FP64, mic [sum n_mic, 3] FP64), contiguous host arrays."""
+    n = len(batch["rt60"])
+    rooms = (Room * n)()
+    for b in range(n):
+        rm = rooms[b]
+        for k in range(3):
+            rm.size[k] = float(batch["size"][b][k])
+        rm.rt60 = float(batch["rt60"][b])
+        rm.fs = float(batch["fs"][b])
+        rm.c = float(batch["c"][b])
+        rm.r_override = float(batch["r_override"][b])
+        rm.seed = int(batch["seed"][b])
+        rm.n_src = int(batch["n_src"][b])
+        rm.n_mic = int(batch["n_mic"][b])
+    src = np.ascontiguousarray(batch["src"], dtype=np.float64)
+    mic = np.ascontiguousarray(batch["mic"], dtype=np.float64)
+    return rooms, n, src, mic
+
+
+def params_struct(params=None, multirate=False):
+    prm = dict(DEFAULT_PARAMS, **(params or {}))
+    return prm, Params(prm["alpha"], prm["beta"], prm["a"], prm["b"], prm["tau"], prm["img_lo"], prm["img_hi"],
+                       FRAMRIR_TAPS, FRAMRIR_FLAG_MULTIRATE if multirate else 0)
+
+
+LAUNCH_FIELDS = ("lds_bytes", "wg_threads", "grid_wgs", "max_mic_group", "waves_per_simd", "bwd_wg_threads",
+                 "bwd_grid_wgs", "render_path")
+
+
+def launch_struct(launch=None):
+    lau = dict(DEFAULT_LAUNCH, **(launch or {}))
+    return lau, Launch(*(int(lau[k]) for k in LAUNCH_FIELDS))
+
+
+def launch_dict(la):
+    return {k: int(getattr(la, k)) for k in LAUNCH_FIELDS}
+
+
+def arch_supported(gcn_arch_name):
+    """framrir_arch_supported: does a device of this gcnArchName run the library."""
+    return bool(lib().framrir_arch_supported(gcn_arch_name.encode()))
+
+
+def size_class(batch):
+    """framrir_size_class: the tuning-cache key of a batch."""
+    rooms, n, _, _ = room_structs(batch)
+    buf = ctypes.create_string_buffer(256)
+    _check(lib().framrir_size_class(rooms, n, buf, 256))
+    return buf.value.decode()
+
+
+class Handle:
+    """framrir_handle of one device: architecture check, the allocation-free
+    entry point's scratch, and the tuning caches (paths: the writable cache
+    first, then read-only fallbacks)."""
+
+    def __init__(self, device=0, cache_paths=()):
+        h = ctypes.c_void_p()
+        _check(lib().framrir_handle_create(int(device), ":".join(cache_paths).encode(), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.framrir_handle_destroy(h)
+            self._h = None
+
+    def tune(self, batch, candidates=None, reps=5, params=None, size_class=None):
+        """framrir_tune: (best launch dict, median ms of its forward)."""
+        rooms, n, src, mic = room_structs(batch)
+        _, p = params_struct(params)
+        cands = None
+        if candidates:
+            cands = (Launch * len(candidates))(*(launch_struct(c)[1] for c in candidates))
+        best = Launch()
+        ms = ctypes.c_double()
+        _check(lib().framrir_tune(self._h, rooms, n, ctypes.byref(p), _np_ptr(src), _np_ptr(mic),
+                                  size_class.encode() if size_class else None, cands,
+                                  len(candidates) if candidates else 0, int(reps), ctypes.byref(best),
+                                  ctypes.byref(ms)))
+        return launch_dict(best), float(ms.value)
+
+    def lookup(self, size_class):
+        """framrir_tune_lookup: (launch dict, found)."""
+        out = Launch()
+        found = ctypes.c_int32()
+        _check(lib().framrir_tune_lookup(self._h, size_class.encode(), ctypes.byref(out), ctypes.byref(found)))
+        return launch_dict(out), bool(found.value)
+
+
 class Plan:
     """Host plan of a batch plus its descriptor blob on the device.
 
@@ -148,27 +250,9 @@ class Plan:
         (forward_multirate only)."""
         import torch
         L = lib()
-        prm = dict(DEFAULT_PARAMS, **(params or {}))
-        lau = dict(DEFAULT_LAUNCH, **(launch or {}))
-        n = len(batch["rt60"])
-        rooms = (Room * n)()
-        for b in range(n):
-            rm = rooms[b]
-            for k in range(3):
-                rm.size[k] = float(batch["size"][b][k])
-            rm.rt60 = float(batch["rt60"][b])
-            rm.fs = float(batch["fs"][b])
-            rm.c = float(batch["c"][b])
-            rm.r_override = float(batch["r_override"][b])
-            rm.seed = int(batch["seed"][b])
-            rm.n_src = int(batch["n_src"][b])
-            rm.n_mic = int(batch["n_mic"][b])
-        self.src = np.ascontiguousarray(batch["src"], dtype=np.float64)
-        self.mic = np.ascontiguousarray(batch["mic"], dtype=np.float64)
-        p = Params(prm["alpha"], prm["beta"], prm["a"], prm["b"], prm["tau"], prm["img_lo"], prm["img_hi"],
-                   FRAMRIR_TAPS, FRAMRIR_FLAG_MULTIRATE if multirate else 0)
-        la = Launch(lau["lds_bytes"], lau["wg_threads"], lau["grid_wgs"], lau["max_mic_group"],
-                    lau["waves_per_simd"], lau["bwd_wg_threads"], lau["bwd_grid_wgs"], lau["render_path"])
+        rooms, n, self.src, self.mic = room_structs(batch)
+        prm, p = params_struct(params, multirate)
+        lau, la = launch_struct(launch)
         handle = ctypes.c_void_p()
         _check(L.framrir_plan_create(rooms, n, ctypes.byref(p), ctypes.byref(la), _np_ptr(self.src),
                                      _np_ptr(self.mic), ctypes.byref(handle)))

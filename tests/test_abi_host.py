@@ -226,3 +226,35 @@ def test_t60_curriculum_schedule():
     assert W.t60_curriculum_range(40, 0.7) == (0.05, 0.7)
     x = W.t60_curriculum_sample(3, 0.7, 1000, seed=1)
     assert np.all((x >= 0.05) & (x <= 0.25)) and np.array_equal(x, W.t60_curriculum_sample(3, 0.7, 1000, seed=1))
+
+
+def test_architecture_check():
+    """The library runs on gfx950 only; framrir_handle_create refuses other
+    devices with E_UNSUPPORTED through this check."""
+    for name in ("gfx950", "gfx950:sramecc+:xnack-", "gfx950:xnack-"):
+        assert fr.arch_supported(name)
+    for name in ("gfx942", "gfx942:sramecc+:xnack-", "gfx90a", "gfx1100", "gfx9500", "gfx95", ""):
+        assert not fr.arch_supported(name)
+
+
+def test_size_class_keys_match_the_shipped_cache():
+    import json
+    from paper_2304_08052_amd import autotune
+    assert fr.size_class(W.config1()) == "fs=16000;mics<=2;T=4096-8192"
+    assert fr.size_class(W.config2()) == "fs=16000;mics<=6;T=1024-16384"
+    assert fr.size_class(W.config3()) == "fs=48000;mics<=8;T=16384-65536"
+    with open(autotune.SHIPPED) as f:
+        shipped = json.load(f)
+    for batch in (W.config2(), W.config3()):
+        assert f"gfx950|{fr.size_class(batch)}" in shipped
+
+
+def test_handle_without_a_gpu_fails_cleanly():
+    """No device in this container: the handle is refused with an error code
+    (no crash, nothing created)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(fr.FramrirError) as e:
+        fr.Handle(0, ())
+    assert e.value.code in (-1, -5)
