@@ -380,8 +380,11 @@ int framrir_multirate_filter(const framrir_plan* plan, const void* desc_dev, flo
  *   mix_dev     out: [n_mic total][n_samples] mixtures, microphones in plan order
  *   gains_dev   out: [n_src] the gains (1 for speaker 0; 0 for a silent source)
  *   ws_dev      workspace of framrir_spatial_workspace bytes, 256-byte aligned
- * RIRs longer than 16384 samples are not supported (FRAMRIR_E_UNSUPPORTED);
- * enqueues only. */
+ * RIRs of up to 16384 samples take one 32768-point FFT per signal block;
+ * longer ones (up to 262144 samples, else FRAMRIR_E_UNSUPPORTED) are cut into
+ * partitions of 16384 samples whose spectra multiply the signal's block
+ * spectra delayed by one block per partition, summed in partition order
+ * (uniformly partitioned overlap-save); enqueues only. */
 int framrir_spatial_workspace(const framrir_plan* plan, int32_t n_samples, size_t* ws_bytes);
 int framrir_spatialize(const framrir_plan* plan, const void* desc_dev, const float* rir_dev, const float* sig_dev,
                        const float* sir_db_dev, const float* snr_db_dev, int32_t n_samples, float* images_dev,

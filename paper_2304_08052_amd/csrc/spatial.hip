@@ -1,6 +1,9 @@
 // gfx950 kernels of the spatialisation step of the on-the-fly training set-up
 // (Sec. IV-A): each dry signal is convolved with its rendered multi-channel
-// RIRs (overlap-save with a 32768-point real FFT held in one workgroup's LDS),
+// RIRs (overlap-save with a 32768-point real FFT held in one workgroup's LDS;
+// an RIR longer than 16384 samples is cut into partitions of 16384 whose
+// spectra multiply the signal's block spectra delayed by one block per
+// partition, summed in partition order: uniformly partitioned overlap-save),
 // the images' energies give the gains of the sampled SIR and SNR, and the
 // scaled images are summed into the mixture.
 //
@@ -231,30 +234,32 @@ __device__ __forceinline__ float2 real_bin(float2 zk, float2 zc, float2 rk) {
 // Spectrum of a real segment of kFftL samples: packed as z[n] = s[2n] + i
 // s[2n+1] and transformed; bins k and N - k both need Z[k] and Z[N - k],
 // which thread pairs (t, 512 - t) exchange through the LDS buffer.  Jobs: one
-// per RIR channel (the RIR at the start of the segment, zeros after it), then
-// one per (source, block j) (signal samples j B - (Tm - 1) + n, zeros outside
+// per (RIR channel, partition p) (RIR samples p Pl .. p Pl + Pl - 1 at the
+// start of the segment, zeros after them; Pl the partition length), then one
+// per (source, block j) (signal samples j B - (Pl - 1) + n, zeros outside
 // [0, N_s)).
 __global__ void __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4)))
 spectrum_kernel(const void* __restrict__ desc, const float* __restrict__ rir, const float* __restrict__ sig,
                 const float2* __restrict__ tw, const float2* __restrict__ rt, float2* __restrict__ hspec,
-                float2* __restrict__ xspec, int n_chan, int n_blk, int adv, int tm, int n_samples) {
+                float2* __restrict__ xspec, int n_chan, int n_part, int n_blk, int adv, int pl, int n_samples) {
     extern __shared__ float2 buf[];
     const int job = blockIdx.x;
     const float* seg;
     int64_t first;          // sample index of segment position 0
     int len;                // valid samples of the source sequence
     float2* dst;
-    if (job < n_chan) {
-        const int b = room_of_chan(desc, job);
+    if (job < n_chan * n_part) {
+        const int c = job / n_part, p = job - c * n_part;
+        const int b = room_of_chan(desc, c);
         const RoomDesc& R = rooms(desc)[b];
-        seg = rir + R.out2_off + static_cast<int64_t>(job - R.chan0) * R.T_out;
+        seg = rir + R.out2_off + static_cast<int64_t>(c - R.chan0) * R.T_out + static_cast<int64_t>(p) * pl;
         first = 0;
-        len = R.T_out;
+        len = min(pl, R.T_out - p * pl);   // may be <= 0: a zero spectrum
         dst = hspec + static_cast<int64_t>(job) * kBins;
     } else {
-        const int q = job - n_chan, s = q / n_blk, j = q % n_blk;
+        const int q = job - n_chan * n_part, s = q / n_blk, j = q % n_blk;
         seg = sig + static_cast<int64_t>(s) * n_samples;
-        first = static_cast<int64_t>(j) * adv - (tm - 1);
+        first = static_cast<int64_t>(j) * adv - (pl - 1);
         len = n_samples;
         dst = xspec + static_cast<int64_t>(q) * kBins;
     }
@@ -298,25 +303,39 @@ spectrum_kernel(const void* __restrict__ desc, const float* __restrict__ rir, co
     if (t == 0) dst[kHalfN] = real_bin(y[0][2], conj2(y[0][2]), rt[kHalfN]);
 }
 
-// One output block of one channel: P = X H, then the inverse real FFT by the
-// forward one: Z[k] = E[k] + i O[k], E = (P[k] + P*[N-k]) / 2, O = (P[k] -
-// P*[N-k]) e^(2 pi i k / L) / 2, z = conj(DFT(conj(Z))) / N, samples 2n and
-// 2n+1 = Re, Im z[n].  Samples Tm - 1 .. L - 1 of the block are the outputs
-// j B .. j B + B - 1 (overlap-save).  Each thread forms P at its own input
+// One output block of one channel: P = sum_p X_(j-p) H_p over the RIR's
+// partitions (block spectra of the signal delayed by p blocks; terms added in
+// partition order), then the inverse real FFT by the forward one: Z[k] = E[k]
+// + i O[k], E = (P[k] + P*[N-k]) / 2, O = (P[k] - P*[N-k]) e^(2 pi i k / L) /
+// 2, z = conj(DFT(conj(Z))) / N, samples 2n and 2n+1 = Re, Im z[n].  Samples
+// Pl - 1 .. Pl - 2 + B of the block are the outputs j B .. j B + B - 1
+// (overlap-save; B = L - Pl + 1 for one partition, B = Pl for several).
+// Each thread forms P at its own input
 // positions k and takes P[N - k] from the thread that formed it, through the
 // LDS buffer half by half (k = 0 pairs with the Nyquist bin P[N], k = N/2
 // with itself); e^(2 pi i k / L) comes from the LDS twiddle tables.
+template <bool PARTS>   // false: one partition (the products need no sum)
 __global__ void __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4)))
 conv_block_kernel(const void* __restrict__ desc, const float2* __restrict__ tw, const float2* __restrict__ hspec,
-                  const float2* __restrict__ xspec, float* __restrict__ images, int n_blk, int adv, int tm,
-                  int n_samples) {
+                  const float2* __restrict__ xspec, float* __restrict__ images, int n_part, int n_blk, int adv,
+                  int pl, int n_samples) {
     extern __shared__ float2 buf[];
     const int c = blockIdx.x / n_blk, j = blockIdx.x % n_blk;
     const int b = room_of_chan(desc, c);
     const RoomDesc& R = rooms(desc)[b];
     const int s = R.src0 + (c - R.chan0) / R.n_mic;
-    const float2* H = hspec + static_cast<int64_t>(c) * kBins;
-    const float2* X = xspec + (static_cast<int64_t>(s) * n_blk + j) * kBins;
+    const float2* H = hspec + static_cast<int64_t>(c) * n_part * kBins;        // partition p at + p kBins
+    const float2* X = xspec + (static_cast<int64_t>(s) * n_blk + j) * kBins;   // block j - p at - p kBins
+    const int n_terms = min(n_part, j + 1);   // blocks before the signal start are zero
+    auto product = [&](int k) {               // sum_p X_(j-p)[k] H_p[k], p ascending
+        float2 acc = cmul(X[k], H[k]);
+        if constexpr (PARTS)
+        for (int p = 1; p < n_terms; ++p) {
+            const float2 v = cmul(X[k - static_cast<int64_t>(p) * kBins], H[k + static_cast<int64_t>(p) * kBins]);
+            acc = make_float2(acc.x + v.x, acc.y + v.y);
+        }
+        return acc;
+    };
     load_twiddles(buf, tw);
     const int t = threadIdx.x;
     // Z[k] needs P[k] = X[k] H[k] and P[N - k].  The thread's positions are
@@ -341,13 +360,13 @@ conv_block_kernel(const void* __restrict__ desc, const float2* __restrict__ tw, 
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int k = t + 512 + 1024 * r;
-        buf[r * kFftThreads + t] = cmul(X[k], H[k]);
+        buf[r * kFftThreads + t] = product(k);
     }
     float2 v[2][16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int k = t + 1024 * r;
-        v[0][r] = cmul(X[k], H[k]);
+        v[0][r] = product(k);
     }
     __syncthreads();
     if (t != 0) {
@@ -361,7 +380,7 @@ conv_block_kernel(const void* __restrict__ desc, const float2* __restrict__ tw, 
             v[0][r] = zform(v[0][r], p, rk);
         }
     } else {
-        const float2 pn = cmul(X[kFftN], H[kFftN]);
+        const float2 pn = product(kFftN);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {   // b = 1: (512 + 1024 r) with (512 + 1024 (15 - r))
             const float2 a1 = buf[r * kFftThreads], b1 = buf[(15 - r) * kFftThreads];
@@ -385,14 +404,15 @@ conv_block_kernel(const void* __restrict__ desc, const float2* __restrict__ tw, 
     fft16k(buf, t1, t1 + kT1, v, y);
     constexpr float inv_n = 1.0f / kFftN;
     float* out = images + static_cast<int64_t>(c) * n_samples;
-    const int o0 = j * adv - (tm - 1);   // output index of segment sample 0 (n_samples < 2^31)
+    const int o0 = j * adv - (pl - 1);   // output index of segment sample 0 (n_samples < 2^31)
+    const int lo = pl - 1, hi = pl - 1 + adv;   // the block's outputs (each written by one block only)
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int n2 = 2 * (static_cast<int>(threadIdx.x) + 512 * i + 4096 * q);
-            if (n2 >= tm - 1 && o0 + n2 < n_samples) out[o0 + n2] = y[i][q].x * inv_n;
-            if (n2 + 1 >= tm - 1 && o0 + n2 + 1 < n_samples) out[o0 + n2 + 1] = -y[i][q].y * inv_n;
+            if (n2 >= lo && n2 < hi && o0 + n2 < n_samples) out[o0 + n2] = y[i][q].x * inv_n;
+            if (n2 + 1 >= lo && n2 + 1 < hi && o0 + n2 + 1 < n_samples) out[o0 + n2 + 1] = -y[i][q].y * inv_n;
         }
 }
 
@@ -478,8 +498,13 @@ __global__ void spatial_mix_kernel(const void* __restrict__ desc, float* __restr
     mix[static_cast<int64_t>(R.mic0) * n_samples + i] = (v0 + v1) + v2;
 }
 
+// RIRs up to kFftN samples: one partition of the RIR's length Tm, blocks of
+// B = L - Tm + 1 outputs.  Longer ones (at most kMaxPart partitions): Pl =
+// kFftN, B = Pl.
+constexpr int kMaxPart = 16;
+
 struct SpatialLayout {
-    int tm, adv, n_blk;
+    int tm, pl, n_part, adv, n_blk;
     int64_t tw_off, rt_off, h_off, x_off, e_off, bytes;
 };
 
@@ -492,16 +517,19 @@ int spatial_layout(const framrir_plan* plan, int32_t n_samples, SpatialLayout& L
             return fr_fail(FRAMRIR_E_INVALID_ARG, "spatialisation needs 3 sources per room (two speakers, the noise)");
         tm = std::max(tm, static_cast<int>(R.T_out));
     }
-    if (tm > kFftN)
-        return fr_fail(FRAMRIR_E_UNSUPPORTED, "RIRs of %d samples: the spatialisation takes at most %d", tm, kFftN);
+    if (tm > kMaxPart * kFftN)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "RIRs of %d samples: the spatialisation takes at most %d", tm,
+                       kMaxPart * kFftN);
     auto align = [](int64_t v) { return (v + 255) & ~int64_t(255); };
     L.tm = tm;
-    L.adv = kFftL - tm + 1;
+    L.n_part = (tm + kFftN - 1) / kFftN;
+    L.pl = L.n_part == 1 ? tm : kFftN;
+    L.adv = kFftL - L.pl + (L.n_part == 1 ? 1 : 0);
     L.n_blk = static_cast<int>((static_cast<int64_t>(n_samples) + L.adv - 1) / L.adv);
     L.tw_off = 0;
     L.rt_off = align(L.tw_off + 8 * static_cast<int64_t>(kFftN));
     L.h_off = align(L.rt_off + 8 * static_cast<int64_t>(kBins));
-    L.x_off = align(L.h_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_chan);
+    L.x_off = align(L.h_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_chan * L.n_part);
     L.e_off = align(L.x_off + 8 * static_cast<int64_t>(kBins) * plan->header.n_src * L.n_blk);
     L.bytes = align(L.e_off + 8 * 4 * static_cast<int64_t>(kEnergyParts) * plan->header.n_rooms);
     return FRAMRIR_OK;
@@ -512,7 +540,10 @@ int allow_fft_lds() {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(spectrum_kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kFftLds);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(conv_block_kernel),
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(conv_block_kernel<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kFftLds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(conv_block_kernel<true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, kFftLds);
         return e == hipSuccess ? 0 : static_cast<int>(e);
     }();
@@ -563,11 +594,16 @@ extern "C" int framrir_spatialize(const framrir_plan* plan, const void* desc_dev
     const int n_chan = plan->header.n_chan, n_src = plan->header.n_src, n_rooms = plan->header.n_rooms;
     hipLaunchKernelGGL(fft_twiddle_kernel, dim3((kBins + 255) / 256), dim3(256), 0, st, tw, rt);
     if (int rc = check("fft_twiddle_kernel")) return rc;
-    hipLaunchKernelGGL(spectrum_kernel, dim3(n_chan + n_src * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev,
-                       rir_dev, sig_dev, tw, rt, hspec, xspec, n_chan, L.n_blk, L.adv, L.tm, n_samples);
+    hipLaunchKernelGGL(spectrum_kernel, dim3(n_chan * L.n_part + n_src * L.n_blk), dim3(kFftThreads), kFftLds, st,
+                       desc_dev, rir_dev, sig_dev, tw, rt, hspec, xspec, n_chan, L.n_part, L.n_blk, L.adv, L.pl,
+                       n_samples);
     if (int rc = check("spectrum_kernel")) return rc;
-    hipLaunchKernelGGL(conv_block_kernel, dim3(n_chan * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev, tw,
-                       hspec, xspec, images_dev, L.n_blk, L.adv, L.tm, n_samples);
+    if (L.n_part == 1)
+        hipLaunchKernelGGL(conv_block_kernel<false>, dim3(n_chan * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev,
+                           tw, hspec, xspec, images_dev, L.n_part, L.n_blk, L.adv, L.pl, n_samples);
+    else
+        hipLaunchKernelGGL(conv_block_kernel<true>, dim3(n_chan * L.n_blk), dim3(kFftThreads), kFftLds, st, desc_dev,
+                           tw, hspec, xspec, images_dev, L.n_part, L.n_blk, L.adv, L.pl, n_samples);
     if (int rc = check("conv_block_kernel")) return rc;
     double* partials = reinterpret_cast<double*>(w + L.e_off);
     hipLaunchKernelGGL(spatial_energy_kernel, dim3(kEnergyParts, n_rooms), dim3(kEnergyThreads), 0, st, desc_dev,

@@ -207,12 +207,13 @@ def edge_cases():
     return _finish(d)
 
 
-def spatial_batch(n_rooms=256, seed=0, rt60_range=(0.1, 0.7)):
+def spatial_batch(n_rooms=256, seed=0, rt60_range=(0.1, 0.7), fs=16000.0, n_mic=4):
     """Rooms for the spatialisation workload (Sec. IV-A, the speed set-up of
     Table 2): rooms U(3,10) x U(3,10) x U(2.5,4) m, T60 U(0.1,0.7) s, 16 kHz,
     three sources per room (two speakers and a point-source noise) 0.3-6 m
     from the array centre, the 4-microphone linear array of the evaluation
-    set (spacings 4, 8, 4 cm), seeds 10000 + b."""
+    set (spacings 4, 8, 4 cm), seeds 10000 + b.  fs and n_mic (2: the array's
+    inner pair) give the long-RIR variants."""
     rng = np.random.default_rng([1006, seed])
     d = _empty()
     for b in range(n_rooms):
@@ -220,9 +221,10 @@ def spatial_batch(n_rooms=256, seed=0, rt60_range=(0.1, 0.7)):
         rt60 = rng.uniform(*rt60_range)
         centre = _inside(rng, size, WALL_MARGIN)
         yaw = rng.uniform(0.0, 2.0 * np.pi)
-        off = np.array([-0.08, -0.04, 0.04, 0.08])
-        mics = np.stack([centre[0] + off * np.cos(yaw), centre[1] + off * np.sin(yaw), np.full(4, centre[2])], axis=1)
-        _add_room(d, rng, size, rt60, 16000.0, 10000 + b, 3, mics)
+        off = np.array([-0.08, -0.04, 0.04, 0.08]) if n_mic == 4 else np.array([-0.04, 0.04])
+        mics = np.stack([centre[0] + off * np.cos(yaw), centre[1] + off * np.sin(yaw), np.full(len(off), centre[2])],
+                        axis=1)
+        _add_room(d, rng, size, rt60, float(fs), 10000 + b, 3, mics)
     return _finish(d)
 
 
@@ -236,7 +238,7 @@ def spatial_signals(batch, n_samples, seed=0):
     rng = np.random.default_rng([2006, seed])
     B, N = len(batch["rt60"]), n_samples
     sig = np.zeros((B, 3, N), dtype=np.float32)
-    t = np.arange(N) / 16000.0
+    t = np.arange(N) / float(batch["fs"][0])
     for b in range(B):
         l1, l2 = (int(rng.uniform(0.75, 1.0) * N) for _ in range(2))
         spans = [(0, l1), (N - l2, N)]

@@ -92,3 +92,19 @@ def room_errors(job):
     fwd = forward_errors((one, got))
     bwd = backward_errors((one, g, gm, gs, gr)) if g is not None else None
     return fwd, bwd
+
+
+def spatial_errors(job):
+    """job = (RIRs [3, M, T], dry signals [3, n], SIR dB, SNR dB, n, GPU
+    images [3, M, n], GPU mixture [M, n], GPU gains [3]): the worst
+    per-channel relative L2 errors of the images and the mixture and the
+    worst relative gain error against the spatialisation oracle (R-28..R-31)."""
+    from oracle import spatialize as SP
+    rir, sig, sir, snr, n, img, mix, g = job
+    want_img, want_mix, want_g = SP.spatialize_room(np.asarray(rir, dtype=np.float64), np.asarray(sig, dtype=np.float64),
+                                                   sir, snr, n)
+    S, M = want_img.shape[:2]
+    e_img = max(rel_l2(np.asarray(img[s, m], dtype=np.float64), want_img[s, m]) for s in range(S) for m in range(M))
+    e_mix = max(rel_l2(np.asarray(mix[m], dtype=np.float64), want_mix[m]) for m in range(M))
+    e_g = float(np.max(np.abs(np.asarray(g, dtype=np.float64) - want_g) / want_g))
+    return e_img, e_mix, e_g

@@ -106,7 +106,34 @@ def test_spatialize_reproducible_and_rejects():
     plan = fr.Plan(W.config4(2))          # one source per room
     with pytest.raises(fr.FramrirError):
         plan.spatial_workspace_bytes(1000)
-    long_batch = W.spatial_batch(1, seed=7)
-    long_batch["rt60"][:] = 1.2           # 19200 samples: longer than one FFT half
+    long_batch = W.spatial_batch(1, seed=7, fs=48000.0)
+    long_batch["rt60"][:] = 5.6           # 268,800 samples: more than 16 partitions of 16,384
     with pytest.raises(fr.FramrirError):
         fr.Plan(long_batch).spatial_workspace_bytes(1000)
+    long_batch["rt60"][:] = 1.2           # 57,600 samples: four partitions, accepted
+    assert fr.Plan(long_batch).spatial_workspace_bytes(1000) > 0
+
+
+def test_spatialize_long_rirs_partitioned(oracle_pool):
+    """RIRs longer than one FFT half (48 kHz, T60 0.45-1.2 s: 21,600-57,600
+    samples, two to four partitions of 16,384) over a 52,000-sample window,
+    so that every partition's delayed block spectra enter the sums: images,
+    mixtures and gains of every room against the FP64 oracle (its direct
+    convolution runs in the worker pool)."""
+    from tests import oracle_pool as P
+    batch = W.spatial_batch(6, seed=9, rt60_range=(0.45, 1.2), fs=48000.0, n_mic=2)
+    n = 52000
+    plan, out, sig, sir, snr, images, mix, gains = _run(batch, n, seed=4)
+    parts = [(int(t) + 16383) // 16384 for t in plan.T]
+    say(f"long RIRs: T {list(plan.T)} partitions {parts}, n = {n}")
+    assert max(parts) == 4 and min(parts) >= 2
+    mo, so = plan.mic_off, plan.src_off
+    jobs = []
+    for b in range(len(plan.T)):
+        M, T = int(plan.n_mic[b]), int(plan.T[b])
+        c0 = 3 * mo[b]
+        jobs.append((out[plan.out_off[b]:plan.out_off[b + 1]].reshape(3, M, T), sig[b], float(sir[b]), float(snr[b]),
+                     n, images[c0:c0 + 3 * M].reshape(3, M, n), mix[mo[b]:mo[b] + M], gains[so[b]:so[b] + 3]))
+    for b, (e_img, e_mix, e_g) in enumerate(oracle_pool.map(P.spatial_errors, jobs, chunksize=1)):
+        say(f"room {b}: T {plan.T[b]} images {e_img:.2e} mix {e_mix:.2e} gains {e_g:.2e}")
+        assert e_img <= TOL and e_mix <= TOL and e_g <= TOL
