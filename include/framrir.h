@@ -249,6 +249,17 @@ int framrir_forward_noalloc(const framrir_plan* plan, const void* desc_dev, doub
                             const double* mic_dev, const double* src_dev, const double* r_dev,
                             float* out_dev, void* stream);
 
+/* framrir_forward plus the early-reverberation windows of Eq. 9 from the
+ * same pass: while the render writes each output sample it also stores the
+ * samples that fall in a channel's window into early_dev (layout, window
+ * rule, zeros outside [0, T) and the start indices in start_dev (may be
+ * NULL) as for framrir_early, whose result this equals bit for bit).
+ * early_dev: early_floats FP32.  Not for multi-rate plans (UNSUPPORTED).
+ * Arguments and errors otherwise as for framrir_forward. */
+int framrir_forward_early(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                          const double* mic_dev, const double* src_dev, const double* r_dev, float* out_dev,
+                          float* early_dev, int32_t* start_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* The two halves of framrir_render.  framrir_prepare (one workgroup per
  * source) computes, into the workspace, each source's fixed-point scale (a
  * bound on the sum of its pulse amplitudes over the microphones) and a copy

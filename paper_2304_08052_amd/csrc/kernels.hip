@@ -458,6 +458,57 @@ __device__ __forceinline__ void load_item(const void* desc, int item, const doub
 }
 
 // ---------------------------------------------------------------------------
+// Early-reverberation windows (Eq. 9) of a channel: its first output index,
+// ceil(t0) - ceil(6 fs / 1000) with t0 = |src - mic| fs / c0 (correctly
+// rounded square root, then one multiply and one divide, in this order).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t early_first(const RoomDesc* R, const double* p, const double* q) {
+    const double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+    const double t0 = (sqrt_rn(dx * dx + dy * dy + dz * dz) * R->fs) / R->c;
+    return static_cast<int64_t>(__builtin_ceil(t0)) - R->early_pre;
+}
+
+// The render's share of the windows, for one item: the windows of its
+// microphones take every output sample the item writes (early_put), and the
+// item that starts a channel (t0 = 0) writes the window's start index and its
+// samples before 0, the one that ends it (t0 + len >= T) those from T on.
+// first: the group's window starts (int32: |start| < 2^31), in LDS.
+struct EarlyItem {
+    float* base;        // window of the group's first microphone (NULL: no windows requested)
+    int width;
+};
+
+__device__ __forceinline__ void early_put(const EarlyItem& E, const int32_t* first, int mm, int64_t n, float v) {
+    const int64_t j = n - first[mm];
+    if (j >= 0 && j < E.width) E.base[static_cast<int64_t>(mm) * E.width + j] = v;
+}
+
+// The group's window starts into LDS (threads tid < mg; the caller
+// synchronises), then zeros outside [0, T) and the start indices.
+__device__ __forceinline__ EarlyItem early_item(const RoomDesc* R, float* __restrict__ early, int local0,
+                                                const double* src_pos, const double* micq, int32_t* first, int mg,
+                                                int tid) {
+    EarlyItem E;
+    E.width = R->early_pre + R->early_post + 1;
+    E.base = early + R->early_off + static_cast<int64_t>(local0) * E.width;
+    if (tid < mg) first[tid] = static_cast<int32_t>(early_first(R, src_pos, micq + 3 * tid));
+    return E;
+}
+
+__device__ __forceinline__ void early_edges(const EarlyItem& E, const int32_t* first, const RoomDesc* R, int local0,
+                                            int mg, int t0, int len, int32_t* __restrict__ start, int tid, int nt) {
+    for (int mm = 0; mm < mg; ++mm) {
+        float* e = E.base + static_cast<int64_t>(mm) * E.width;
+        if (t0 == 0) {
+            for (int64_t j = tid; j < E.width && first[mm] + j < 0; j += nt) e[j] = 0.0f;
+            if (start && tid == 0) start[R->chan0 + local0 + mm] = static_cast<int32_t>(first[mm]);
+        }
+        if (t0 + len >= R->T)
+            for (int64_t j = max(int64_t(0), R->T - first[mm]) + tid; j < E.width; j += nt) e[j] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Render: fixed-point scale, preparation and the scatter kernel
 // ---------------------------------------------------------------------------
 // Fixed-point budget of the LDS accumulators.  A sample n of a source's RIR
@@ -857,14 +908,16 @@ __device__ __forceinline__ void pool_round(int* __restrict__ acc, uint32_t* __re
     wave_sync();
 }
 
-template <int NT, int WPE>
+template <int NT, int WPE, bool EARLY>   // EARLY: the Eq. 9 windows are written too
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 render_kernel(const void* __restrict__ desc, const double* __restrict__ table, const double* __restrict__ mic,
               const double* __restrict__ src, const double* __restrict__ r_in, float* __restrict__ out,
               int* __restrict__ counters, const float* __restrict__ src_scale, const int* __restrict__ bucket_off,
-              const double* __restrict__ sorted, int acc_words) {
+              const double* __restrict__ sorted, int acc_words, float* __restrict__ early,
+              int32_t* __restrict__ early_start) {
     extern __shared__ int acc[];
     __shared__ double micq[3 * kMaxMicGroup];
+    __shared__ int32_t s_efirst[kMaxMicGroup];        // early windows: starts of the group's channels
     __shared__ int s_item;
     __shared__ uint32_t stage[NT / 64][3 * kPool];   // per wave: staged pairs of a round
     __shared__ int bank_cnt[NT / 64][kLdsBanks];
@@ -951,13 +1004,24 @@ render_kernel(const void* __restrict__ desc, const double* __restrict__ table, c
         // clearing of every accumulator the item touched
         const int nvalid = min(c.w.len, c.T - c.w.t0);
         const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
+        const int local0 = c.s_local * c.n_mic_room + c.w.mic0;   // the group's first channel in the room
+        EarlyItem E{nullptr, 0};
+        if constexpr (EARLY) {
+            const RoomDesc* R = rooms(desc) + c.room;
+            E = early_item(R, early, local0, src + 3 * c.w.src, micq, s_efirst, mg, tid);
+            __syncthreads();
+            early_edges(E, s_efirst, R, local0, mg, c.w.t0, c.w.len, early_start, tid, NT);
+        }
         for (int mm = 0; mm < mg; ++mm) {
-            float* dst = out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + mm) * c.T +
-                         c.w.t0;
+            float* dst = out + c.out_off + static_cast<int64_t>(local0 + mm) * c.T + c.w.t0;
             int* row = acc + mm * c.rowlen;
             for (int k = tid; k < c.rowlen; k += NT) {
                 const int v = row[k];
-                if (k >= kHalo && k < kHalo + nvalid) dst[k - kHalo] = static_cast<float>(v) * inv;
+                if (k >= kHalo && k < kHalo + nvalid) {
+                    const float h = static_cast<float>(v) * inv;
+                    dst[k - kHalo] = h;
+                    if constexpr (EARLY) early_put(E, s_efirst, mm, c.w.t0 + k - kHalo, h);
+                }
                 row[k] = 0;
             }
         }
@@ -1163,14 +1227,17 @@ __device__ __forceinline__ void mom_walk_init(MomWalk& w, const ItemCtx& c, cons
     if (tid < w.n_pairs) w.row = w.rows[w.j];
 }
 
-template <int NT, int WPE>
+template <int NT, int WPE, bool EARLY>   // EARLY: the Eq. 9 windows are written too
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
-render_moment_kernel(const void* __restrict__ desc, const double* __restrict__ mic, const double* __restrict__ r_in,
-                     float* __restrict__ out, int* __restrict__ counters, const float* __restrict__ src_scale,
-                     const int* __restrict__ bucket_off, const double* __restrict__ sorted, int lds_words) {
+render_moment_kernel(const void* __restrict__ desc, const double* __restrict__ mic, const double* __restrict__ src,
+                     const double* __restrict__ r_in, float* __restrict__ out, int* __restrict__ counters,
+                     const float* __restrict__ src_scale, const int* __restrict__ bucket_off,
+                     const double* __restrict__ sorted, int lds_words, float* __restrict__ early,
+                     int32_t* __restrict__ early_start) {
     extern __shared__ u32x4 lds_v[];
     int* lds = reinterpret_cast<int*>(lds_v);
     __shared__ double micq[3 * kMaxMicGroup];
+    __shared__ int32_t s_efirst[kMaxMicGroup];        // early windows: starts of the group's channels
     __shared__ int s_item;
     const DescHeader* H = hdr(desc);
     const int n_items = H->n_items;
@@ -1256,6 +1323,14 @@ render_moment_kernel(const void* __restrict__ desc, const double* __restrict__ m
         const int col = lane & 15, grp = lane >> 4;
         const int end = min(c.w.t0 + c.w.len, c.T);
         const int nb = mg * nblk;
+        const int local0 = c.s_local * c.n_mic_room + c.w.mic0;   // the group's first channel in the room
+        EarlyItem E{nullptr, 0};
+        if constexpr (EARLY) {   // (micq still holds this item's microphones)
+            const RoomDesc* Rr = rooms(desc) + c.room;
+            E = early_item(Rr, early, local0, src + 3 * c.w.src, micq, s_efirst, mg, tid);
+            __syncthreads();
+            early_edges(E, s_efirst, Rr, local0, mg, c.w.t0, c.w.len, early_start, tid, NT);
+        }
         for (int g0 = wave; g0 < nb; g0 += NW * kMomGroup) {
             f32x4 acc[kMomGroup];
             int eo0[kMomGroup], mo0[kMomGroup];
@@ -1319,11 +1394,14 @@ render_moment_kernel(const void* __restrict__ desc, const double* __restrict__ m
                 const int n = c.w.t0 + off;
                 const i32x4 d =
                     *reinterpret_cast<const i32x4*>(lds + mm * mic_words + kMomPow * Rw + mom_word(off + kHalf));
-                float* dst =
-                    out + c.out_off + (static_cast<int64_t>(c.s_local) * c.n_mic_room + c.w.mic0 + mm) * c.T;
+                float* dst = out + c.out_off + static_cast<int64_t>(local0 + mm) * c.T;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (n + r < end) dst[n + r] = __builtin_fmaf(acc[i][r], inv_mom, static_cast<float>(d[r]) * inv);
+                    if (n + r < end) {
+                        const float h = __builtin_fmaf(acc[i][r], inv_mom, static_cast<float>(d[r]) * inv);
+                        dst[n + r] = h;
+                        if constexpr (EARLY) early_put(E, s_efirst, mm, n + r, h);
+                    }
             }
         }
         __syncthreads();
@@ -1671,12 +1749,7 @@ __global__ void __launch_bounds__(256) early_kernel(const void* __restrict__ des
         const int width = R->early_pre + R->early_post + 1;
         for (int local = blockIdx.z; local < n_chan; local += gridDim.z) {
             const int s = local / R->n_mic, m = local % R->n_mic;
-            // t0 = |src - mic| fs / c0, one rounding per operation in this order
-            const double* p = src + 3 * (R->src0 + s);
-            const double* q = mic + 3 * (R->mic0 + m);
-            const double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
-            const double t0 = (sqrt_rn(dx * dx + dy * dy + dz * dz) * R->fs) / R->c;
-            const int64_t first = static_cast<int64_t>(__builtin_ceil(t0)) - R->early_pre;
+            const int64_t first = early_first(R, src + 3 * (R->src0 + s), mic + 3 * (R->mic0 + m));
             const float* h = out + R->out_off + static_cast<int64_t>(local) * R->T;
             float* e = early + R->early_off + static_cast<int64_t>(local) * width;
             for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < width; j += gridDim.x * blockDim.x) {
@@ -2102,7 +2175,8 @@ int launch_prepare(const framrir_plan* plan, const void* desc_dev, double* table
 }
 
 int launch_render(const framrir_plan* plan, const void* desc_dev, const double* table_dev, const double* mic_dev,
-                  const double* src_dev, const double* r_dev, float* out_dev, void* ws_dev, hipStream_t st) {
+                  const double* src_dev, const double* r_dev, float* out_dev, void* ws_dev, hipStream_t st,
+                  float* early_dev = nullptr, int32_t* start_dev = nullptr) {
     const RenderWs w = render_ws(plan, ws_dev);
     const int lds = plan->launch.lds_bytes;
     const int acc_words = plan->launch.lds_bytes / 4;
@@ -2110,11 +2184,19 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
     const int key = plan->launch.wg_threads * 16 + plan->launch.waves_per_simd;
     if (plan->launch.render_path == 1) {   // compiled at 4 waves per SIMD only (the plan checks it)
         switch (key) {
-#define FR_CASE(NT)                                                                                         \
-    case NT * 16 + 4:                                                                                       \
-        if (int rc = allow_lds<render_moment_kernel<NT, 4>, kLdsPerCu - kMomStaticLds>()) return rc;        \
-        hipLaunchKernelGGL((render_moment_kernel<NT, 4>), grid, block, lds, st, desc_dev, mic_dev, r_dev,   \
-                           out_dev, w.counters, w.src_scale, w.bucket_off, w.sorted, acc_words);            \
+#define FR_CASE(NT)                                                                                          \
+    case NT * 16 + 4:                                                                                        \
+        if (early_dev) {                                                                                     \
+            if (int rc = allow_lds<render_moment_kernel<NT, 4, true>, kLdsPerCu - kMomStaticLds>()) return rc; \
+            hipLaunchKernelGGL((render_moment_kernel<NT, 4, true>), grid, block, lds, st, desc_dev, mic_dev, \
+                               src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off, w.sorted,     \
+                               acc_words, early_dev, start_dev);                                             \
+        } else {                                                                                             \
+            if (int rc = allow_lds<render_moment_kernel<NT, 4, false>, kLdsPerCu - kMomStaticLds>()) return rc; \
+            hipLaunchKernelGGL((render_moment_kernel<NT, 4, false>), grid, block, lds, st, desc_dev, mic_dev, \
+                               src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off, w.sorted,     \
+                               acc_words, nullptr, nullptr);                                                 \
+        }                                                                                                    \
         break;
             FR_CASE(256) FR_CASE(512) FR_CASE(1024)
 #undef FR_CASE
@@ -2125,12 +2207,19 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
         return check_launch("render_moment_kernel");
     }
     switch (key) {
-#define FR_CASE(NT, WPE)                                                                                    \
-    case NT * 16 + WPE:                                                                                     \
-        if (int rc = allow_lds<render_kernel<NT, WPE>, kLdsPerCu - render_static_lds(NT)>()) return rc;     \
-        hipLaunchKernelGGL((render_kernel<NT, WPE>), grid, block, lds, st, desc_dev, table_dev, mic_dev,   \
-                           src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off, w.sorted,         \
-                           acc_words);                                                                      \
+#define FR_CASE(NT, WPE)                                                                                     \
+    case NT * 16 + WPE:                                                                                      \
+        if (early_dev) {                                                                                     \
+            if (int rc = allow_lds<render_kernel<NT, WPE, true>, kLdsPerCu - render_static_lds(NT)>()) return rc; \
+            hipLaunchKernelGGL((render_kernel<NT, WPE, true>), grid, block, lds, st, desc_dev, table_dev,    \
+                               mic_dev, src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off,     \
+                               w.sorted, acc_words, early_dev, start_dev);                                   \
+        } else {                                                                                             \
+            if (int rc = allow_lds<render_kernel<NT, WPE, false>, kLdsPerCu - render_static_lds(NT)>()) return rc; \
+            hipLaunchKernelGGL((render_kernel<NT, WPE, false>), grid, block, lds, st, desc_dev, table_dev,   \
+                               mic_dev, src_dev, r_dev, out_dev, w.counters, w.src_scale, w.bucket_off,     \
+                               w.sorted, acc_words, nullptr, nullptr);                                       \
+        }                                                                                                    \
         break;
         FR_KERNEL_SHAPES(FR_CASE)
 #undef FR_CASE
@@ -2276,6 +2365,23 @@ extern "C" int framrir_forward_noalloc(const framrir_plan* plan, const void* des
     if ((rc = check_launch("zero_counters_kernel"))) return rc;
     if ((rc = launch_prepare(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, ws, st, true))) return rc;
     return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws, st);
+}
+
+extern "C" int framrir_forward_early(const framrir_plan* plan, const void* desc_dev, double* table_dev,
+                                     const double* mic_dev, const double* src_dev, const double* r_dev,
+                                     float* out_dev, float* early_dev, int32_t* start_dev, void* ws_dev,
+                                     size_t ws_bytes, void* stream) {
+    if (plan && plan->header.multirate)
+        return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: the early windows are taken at the output rate");
+    if (!early_dev) return fr_fail(FRAMRIR_E_INVALID_ARG, "early_dev is NULL (use framrir_forward)");
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_bytes : 0);
+    if (rc) return rc;
+    if (!aligned(early_dev, 4)) return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned early_dev");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = launch_prepare(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, ws_dev, st, true))) return rc;
+    return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws_dev, st, early_dev,
+                         start_dev);
 }
 
 namespace {

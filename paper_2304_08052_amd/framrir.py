@@ -68,6 +68,7 @@ EXPORTS = {
     "framrir_render": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_forward": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_forward_noalloc": (ctypes.c_int, [ctypes.c_void_p] * 8),
+    "framrir_forward_early": (ctypes.c_int, [ctypes.c_void_p] * 10 + [ctypes.c_size_t, ctypes.c_void_p]),
     "framrir_prepare": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                                                ctypes.c_void_p]),
     "framrir_render_prepared": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
@@ -341,6 +342,25 @@ class Plan:
         _check(lib().framrir_forward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
                                      _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out, table
+
+    def forward_early(self, table=None, mic=None, src=None, r=None, out=None, early=None, start=None, ws=None,
+                      stream=None, desc=None):
+        """framrir_forward_early: the forward and the Eq. 9 windows from the
+        same pass; returns (out, table, early, start)."""
+        import torch
+        table = self.empty_table() if table is None else table
+        out = self.empty_out() if out is None else out
+        early = torch.empty(self.info.early_floats, dtype=torch.float32, device=self.device) if early is None \
+            else early
+        start = torch.empty(self.info.n_chan, dtype=torch.int32, device=self.device) if start is None else start
+        ws = self.workspace() if ws is None else ws
+        mic = self.mic_dev if mic is None else mic
+        src = self.src_dev if src is None else src
+        desc = self.desc if desc is None else desc
+        _check(lib().framrir_forward_early(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
+                                           _ptr(out), _ptr(early), _ptr(start), _ptr(ws), ws.numel(),
+                                           _stream(stream)))
+        return out, table, early, start
 
     def forward_noalloc(self, table, out, mic=None, src=None, r=None, stream=None, desc=None):
         """framrir_forward_noalloc: the forward with the library's static

@@ -93,3 +93,38 @@ def test_early_full_workloads(which):
     plan, out, early, start = _run(batch, launch=autotune.launch_for(batch))
     assert np.array_equal(start.astype(np.int64), _oracle_starts(batch))
     _check_windows_equal_output(plan, out, early, start)
+
+
+@pytest.mark.parametrize("which,launch", [
+    ("edges", None),
+    ("edge_cases", None),
+    ("small_mixed", dict(lds_bytes=16384, wg_threads=256, max_mic_group=2)),   # many time tiles
+    ("small_mixed", dict(lds_bytes=65536, wg_threads=512, max_mic_group=2, render_path=1)),
+    ("edge_cases", dict(lds_bytes=65536, wg_threads=512, max_mic_group=1, render_path=1)),
+    ("config2", "tuned"),
+])
+def test_early_fused_in_render(which, launch):
+    """framrir_forward_early: the windows come from the render pass itself
+    (every output sample stored once more when it lies in its channel's
+    window, the edge items writing the zeros and the start indices): the RIRs
+    equal framrir_forward's and the windows and starts equal framrir_early's,
+    bit for bit, in both render paths and under time tiling."""
+    import torch
+    from paper_2304_08052_amd import autotune
+    from paper_2304_08052_amd import framrir as fr
+    batch = dict(small_mixed=lambda: W.small_mixed(6, seed=31), edges=_edge_batch, edge_cases=W.edge_cases,
+                 config2=W.config2)[which]()
+    if launch == "tuned":
+        launch = autotune.launch_for(batch)
+    say(f"fused early windows {which} launch={launch}")
+    plan = fr.Plan(batch, launch=launch)
+    early_f = torch.full((plan.info.early_floats,), float("nan"), dtype=torch.float32, device="cuda")
+    start_f = torch.full((plan.info.n_chan,), -7, dtype=torch.int32, device="cuda")
+    out_f, _, early_f, start_f = plan.forward_early(early=early_f, start=start_f)
+    out, _ = plan.forward()
+    early, start = plan.early(out)
+    torch.cuda.synchronize()
+    assert torch.equal(out_f, out)
+    assert torch.equal(start_f, start)
+    assert torch.equal(early_f, early), "fused windows differ from the separate early kernel"
+    assert np.array_equal(start.cpu().numpy().astype(np.int64), _oracle_starts(batch))
