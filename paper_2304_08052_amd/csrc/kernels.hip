@@ -861,14 +861,17 @@ __device__ __forceinline__ void pool_round(int* __restrict__ acc, uint32_t* __re
     if (a.word >= 0) ra = atomicAdd(&cnt[ka], 1);
     if (b.word >= 0) rb = atomicAdd(&cnt[kb], 1);
     wave_sync();
-    // exclusive scan of the bank counts (lanes 0..31)
+    // exclusive scan of the bank counts (lanes 0..31) in registers (DPP row
+    // shifts, then lane 15 broadcast into the next row), not through the LDS
+    // queue that the tap atomics keep busy
     const int cv = lane < kLdsBanks ? cnt[lane] : 0;
     int incl = cv;
-    for (int off = 1; off < kLdsBanks; off <<= 1) {
-        const int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
-    }
-    const int n_pool = __shfl(incl, kLdsBanks - 1);
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);   // row_shr:1
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);   // row_shr:2
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);   // row_shr:4
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xf, 0xf, false);   // row_shr:8
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    const int n_pool = __builtin_amdgcn_readlane(incl, kLdsBanks - 1);
     wave_sync();
     if (lane < kLdsBanks) cnt[lane] = incl - cv;
     wave_sync();
