@@ -355,21 +355,22 @@ int framrir_early(const framrir_plan* plan, const void* desc_dev, const double* 
  * L - 1) (D correctly rounded, FP64), the impulse r^g / D at q down-sampled to
  * r_l fs with the 81-tap Hann-windowed sinc (unit peak) into inter_dev[0 ..
  * mr_floats) (packed [S][M][T_l], T_l = ceil(T60 r_l fs)), an 80 Hz
- * second-order Butterworth high-pass (bilinear, prewarped; FP64 recurrence,
- * exact chunked evaluation, its partial chunk responses in inter_dev[mr_floats ..
- * 2 mr_floats) as scratch), and the decimation by r_l with the same pulse in
- * units of fs: out_dev (out_floats FP32, packed [S][M][T], T = ceil(T60 fs)).
- * inter_dev: 2 * mr_floats FP32; ws_dev: ws_mr_bytes, initialised as for
- * framrir_render.  Enqueue only.  Errors: INVALID_ARG, WORKSPACE,
+ * second-order Butterworth high-pass from rest (bilinear, prewarped; FP64
+ * recurrence, exact chunked evaluation: the output state at every 256-sample
+ * chunk start is found first, then re-run from there), and the decimation by
+ * r_l with the same pulse in units of fs: out_dev (out_floats FP32, packed
+ * [S][M][T], T = ceil(T60 fs)).  inter_dev: mr_floats FP32; ws_dev:
+ * ws_mr_bytes, initialised as for framrir_render.  Enqueue only.  Errors:
+ * INVALID_ARG, WORKSPACE,
  * UNSUPPORTED (not a multi-rate plan), DEVICE. */
 int framrir_forward_multirate(const framrir_plan* plan, const void* desc_dev, double* table_dev,
                               const double* mic_dev, const double* src_dev, const double* r_dev, float* inter_dev,
                               float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* The stages of framrir_forward_multirate after the render: the high-pass of
- * the intermediate signal inter_dev[0 .. mr_floats) (scratch in inter_dev
- * [mr_floats .. 2 mr_floats)) and the decimation into out_dev.  Arguments and
- * errors as for framrir_forward_multirate. */
+ * the intermediate signal inter_dev[0 .. mr_floats) (read only) and the
+ * decimation into out_dev.  Arguments and errors as for
+ * framrir_forward_multirate. */
 int framrir_multirate_filter(const framrir_plan* plan, const void* desc_dev, float* inter_dev, float* out_dev,
                              void* ws_dev, size_t ws_bytes, void* stream);
 

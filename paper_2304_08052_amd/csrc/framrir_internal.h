@@ -80,6 +80,7 @@ struct RoomDesc {
     double rl, rh;             // r_l, r_h
     double hp_b0, hp_a1, hp_a2;   // 80 Hz Butterworth high-pass: b = b0 (1, -2, 1), a = (1, a1, a2)
     double phi[4];             // state transition of the high-pass over one chunk (row-major)
+    double phi_sub[8][4];      // the same over j sub-chunks of kHpSub samples, j = 0 .. 7
     int64_t out2_off;          // first float of the room in the output at fs
     int64_t chunk0;            // first high-pass chunk of the room
     int32_t T_out;             // ceil(T60 fs)
@@ -87,17 +88,17 @@ struct RoomDesc {
 };
 
 constexpr int kHpChunk = 256;         // intermediate samples per high-pass chunk
-constexpr int kHpBatch = 32;          // samples a high-pass thread loads at once
-constexpr int kDecThreads = 64;       // threads per decimation block
-constexpr int kDecPerThread = 8;      // consecutive outputs per decimation thread
-constexpr int kDecOut = kDecThreads * kDecPerThread;   // output samples per decimation tile
+constexpr int kHpSub = 32;            // samples per sub-chunk (one thread's run of the recursion)
 constexpr int kMaxRl = 12;            // largest r_l a multi-rate plan accepts
-constexpr int kHpBasisStride = 2 * kHpChunk;   // doubles per room: unforced responses ha, hb
-// Decimation taps k[u] = P(u / r_l), stored phase-major per room: row q
-// (u = m r_l + q, 0 <= q < r_l) holds k at m = M0 .. M1, M1 = -M0 =
-// ceil(half / r_l) + 2 kDecPerThread (zero outside |u| <= half), so the taps
-// one super-step needs are consecutive floats.  Floats per room, widest r_l:
-constexpr int kDecTapStride = kMaxRl * (2 * (41 + 2 * kDecPerThread) + 1);
+// Decimation on the matrix cores: a workgroup of kDmThreads takes kDmBlocks
+// blocks of 256 outputs (one per wave).  The filter matrix of an r_l, W[i][q]
+// = k[i r_l + half + pad - q] (16 x K, K <= 32 kDmMaxSteps), is kept per r_l
+// (1 .. kMaxRl) as fp16 hi / lo fragments: kDmFragWords 32-bit words each.
+constexpr int kDmBlocks = 4;
+constexpr int kDmThreads = 64 * kDmBlocks;
+constexpr int kDmOut = 256 * kDmBlocks;          // outputs per workgroup tile
+constexpr int kDmMaxSteps = 37;                  // ceil((7 + 15 r_l + 2 half + 1) / 32) at r_l = 12
+constexpr int kDmFragWords = kDmMaxSteps * 2 * 64 * 4;
 
 struct SrcDesc {
     double d0, q, ct, rrmax;   // |src - centre|, c0T60 / d0, c0T60, RR_max (Eq. 5)

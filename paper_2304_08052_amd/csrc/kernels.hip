@@ -1768,155 +1768,140 @@ __global__ void __launch_bounds__(256) early_kernel(const void* __restrict__ des
 // Multi-rate chain after the render (Sec. II): 80 Hz high-pass at r_l fs, then
 // decimation by r_l.
 // ---------------------------------------------------------------------------
-// High-pass y[n] = b0 (x[n] - 2 x[n-1] + x[n-2]) - a1 y[n-1] - a2 y[n-2] (FP64)
-// over chunks of kHpChunk samples evaluated in parallel and exactly: every
-// chunk is first filtered with its true input history and its output history
-// set equal to that input history, (y[s-1], y[s-2]) := (x[s-1], x[s-2]); the
-// deviations d = y - x of the true output states at the chunk starts are then
-// carried from chunk to chunk through the chunk's state transition phi, and
-// each chunk adds the unforced response of its deviation.  (Starting from
-// y = x rather than y = 0 keeps the stored FP32 part of the size of the
-// output: from a zero output state the slow poles near z = 1 make the partial
-// response grow across the chunk, about the chunk length times the input's
-// slope at its start, and the unforced response cancels that growth, leaving
-// the FP32 rounding of the partial response amplified by that cancellation.)
-// One wave per 64 consecutive chunks of a channel (lane =
-// chunk); batches of kHpBatch samples go through LDS, so that the global
-// loads and stores are whole 128-byte lines while each lane runs its chunk's
-// recurrence.  Blocks: (chunks / 64, rooms, channels of the room).
+// High-pass y[n] = b0 (x[n] - 2 x[n-1] + x[n-2]) - a1 y[n-1] - a2 y[n-2] (FP64),
+// from rest, evaluated in parallel and exactly: the deviation d = y - x of the
+// output state, (y[s-1] - x[s-1], y[s-2] - x[s-2]), is found at every
+// sub-chunk start s (kHpSub samples apart) before the decimation runs, which
+// then runs the recurrence from those states over just the samples it needs.
+// The deviations come from partial runs: a span filtered with its true input
+// history and its output history set equal to that input history (deviation
+// 0) ends at deviation e; the true run, starting at deviation d, differs from
+// it by the unforced response of d, so it ends at e + phi d (phi the span's
+// state transition).  hp_chunk_end_kernel: partial runs over the sub-chunks,
+// one thread each, combined in order within each chunk into the chunk's
+// partial run: its deviation p_j at sub-chunk j's start and e(k) at its end;
+// hp_carry_kernel: one thread per channel carries the chunk starts, d(k + 1) =
+// e(k) + phi d(k); sub-chunk j of chunk k then starts at p_j + phi_sub[j] d(k).
 
-// Coalesced move of one batch (samples off .. off + kHpBatch of 64 chunks)
-// between global memory g (the channel's first sample) and buf[chunk][i]:
-// instruction it moves sample i = lane mod kHpBatch of chunks 2 it and
-// 2 it + 1.  Loads: all kHpBatch global loads of a lane are issued before
-// the first LDS write (out-of-range lanes load the channel's first sample and
-// write 0), so a wave has the whole batch in flight; stores: the batch is
-// read from LDS first, then stored.
-template <bool LOAD>
-__device__ __forceinline__ void hp_batch_move(float* __restrict__ g, float (*buf)[kHpBatch + 1], int kbase, int off,
-                                              const RoomDesc* R) {
-    static_assert(kHpBatch == 32, "two chunks per instruction");
-    const int lane = threadIdx.x;
-    const int i = lane & (kHpBatch - 1), half = lane / kHpBatch;
-    float v[kHpBatch];
-    if constexpr (LOAD) {
-#pragma unroll
-        for (int it = 0; it < kHpBatch; ++it) {
-            const int kc = kbase + 2 * it + half;
-            const int n = kc * kHpChunk + off + i;
-            const bool ok = kc < R->n_chunks && n < R->T;
-            v[it] = g[ok ? static_cast<unsigned>(n) : 0u];
-        }
-#pragma unroll
-        for (int it = 0; it < kHpBatch; ++it) {
-            const int kc = kbase + 2 * it + half;
-            const int n = kc * kHpChunk + off + i;
-            const bool ok = kc < R->n_chunks && n < R->T;
-            buf[2 * it + half][i] = ok ? v[it] : 0.0f;
-        }
-    } else {
-#pragma unroll
-        for (int it = 0; it < kHpBatch; ++it) v[it] = buf[2 * it + half][i];
-#pragma unroll
-        for (int it = 0; it < kHpBatch; ++it) {
-            const int kc = kbase + 2 * it + half;
-            const int n = kc * kHpChunk + off + i;
-            if (kc < R->n_chunks && n < R->T) g[n] = v[it];
-        }
-    }
+// Raw buffer view of n floats at p: loads at byte offsets >= 4 n return 0
+// (range checking of untyped buffer accesses with stride 0; word 3 selects
+// the 32-bit data format).  The check covers the VGPR offset and the
+// instruction's immediate offset but not the SGPR offset, so every access
+// passes its whole offset in the VGPR operand; offsets before the start are
+// given as 2^31 bytes, past any view.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const float* p, int n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), static_cast<short>(0), 4 * n, 0x00020000);
+}
+// (The b32 builtin moves 32-bit integers: the floats go through a bit cast.)
+__device__ __forceinline__ float view_load(__amdgpu_buffer_rsrc_t v, int64_t i) {
+    const int off = i >= 0 ? static_cast<int>(4 * i) : INT32_MIN;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v, off, 0, 0));
 }
 
-__global__ void __launch_bounds__(64) hp_zero_state_kernel(const void* __restrict__ desc,
-                                                           const float* __restrict__ x, float* __restrict__ y,
-                                                           double* __restrict__ zend) {
-    __shared__ float buf[64][kHpBatch + 1];
+// One step of the high-pass in direct form, the feedback as FMAs: the
+// dependence from one output to the next is a single FMA.
+__device__ __forceinline__ double hp_step(double xn, double& x1, double& x2, double& y1, double& y2, double b0,
+                                          double a1, double a2) {
+    const double yn = __builtin_fma(-a1, y1, __builtin_fma(-a2, y2, b0 * ((xn - 2.0 * x1) + x2)));
+    x2 = x1;
+    x1 = xn;
+    y2 = y1;
+    y1 = yn;
+    return yn;
+}
+
+// Deviation at the end of the partial run over one sub-chunk (32 samples in
+// registers, input history x1, x2).
+__device__ __forceinline__ double2 hp_sub_partial(const float (&xr)[kHpSub], double x1, double x2, double b0,
+                                                  double a1, double a2) {
+    double y1 = x1, y2 = x2;
+#pragma unroll
+    for (int i = 0; i < kHpSub; ++i) hp_step(xr[i], x1, x2, y1, y2, b0, a1, a2);
+    return double2{y1 - x1, y2 - x2};
+}
+
+// LDS word of sample w of a staged run: one pad word after every 32, so that
+// thread t's sub-chunk (words 33 t ..) and consecutive samples both spread
+// over the banks.
+__device__ __forceinline__ int hp_word(int w) { return w + (w >> 5); }
+
+constexpr int kHpEndChunks = 32;                         // chunks per hp_chunk_end_kernel block
+constexpr int kHpSubPerChunk = kHpChunk / kHpSub;        // 8
+constexpr int kHpEndThreads = kHpEndChunks * kHpSubPerChunk;
+static_assert(kHpEndThreads == 256 && kHpSub == 32, "one sub-chunk per thread, 32 chunks per block");
+
+// Partial deviations of every chunk: block = 32 consecutive chunks of a
+// channel (8192 samples, loaded coalesced into LDS), thread = sub-chunk; the
+// sub-chunk end deviations e_j are combined in order by one thread per chunk,
+// p_0 = 0, p_(j+1) = e_j + phi_sub[1] p_j: p_j to sub (one per sub-chunk), p_8
+// = e(k) to zend.  Blocks: (chunks / 32, rooms, channels).
+__global__ void __launch_bounds__(kHpEndThreads) hp_chunk_end_kernel(const void* __restrict__ desc,
+                                                                     const float* __restrict__ x,
+                                                                     double* __restrict__ zend,
+                                                                     double2* __restrict__ sub) {
+    constexpr int kSamples = kHpEndChunks * kHpChunk;
+    __shared__ float xs[kSamples + kSamples / 32];
+    __shared__ double2 es[kHpEndThreads];
     const DescHeader* H = hdr(desc);
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     for (int b = blockIdx.y; b < H->n_rooms; b += gridDim.y) {
         const RoomDesc* R = rooms(desc) + b;
-        const int kbase = blockIdx.x * 64;
-        if (kbase >= R->n_chunks) continue;
+        const int c0 = blockIdx.x * kHpEndChunks;
+        if (c0 >= R->n_chunks) continue;
+        const double b0 = R->hp_b0, a1 = R->hp_a1, a2 = R->hp_a2;
         for (int local = blockIdx.z; local < R->n_src * R->n_mic; local += gridDim.z) {
-            const int64_t base = R->out_off + static_cast<int64_t>(local) * R->T;
-            const int k = kbase + lane;
-            const bool live = k < R->n_chunks;
-            const int s0 = k * kHpChunk, s1 = min(R->T, s0 + kHpChunk);
-            const double b0 = R->hp_b0, a1 = R->hp_a1, a2 = R->hp_a2;
-            double x1 = 0.0, x2 = 0.0;
-            if (live && s0 >= 1) x1 = x[base + s0 - 1];
-            if (live && s0 >= 2) x2 = x[base + s0 - 2];
-            double y1 = x1, y2 = x2;   // output history := input history
-            for (int off = 0; off < kHpChunk; off += kHpBatch) {
-                __syncthreads();
-                hp_batch_move<true>(const_cast<float*>(x) + base, buf, kbase, off, R);
-                __syncthreads();
-                if (live) {
-                    for (int i = 0; i < kHpBatch && s0 + off + i < s1; ++i) {
-                        const double xn = buf[lane][i];
-                        const double yn = b0 * ((xn - 2.0 * x1) + x2) - a1 * y1 - a2 * y2;
-                        buf[lane][i] = static_cast<float>(yn);
-                        x2 = x1;
-                        x1 = xn;
-                        y2 = y1;
-                        y1 = yn;
-                    }
+            const __amdgpu_buffer_rsrc_t xv = buffer_view(x + R->out_off + static_cast<int64_t>(local) * R->T, R->T);
+            const int64_t s0 = static_cast<int64_t>(c0) * kHpChunk;   // first sample of the block
+            float v[kSamples / kHpEndThreads];
+#pragma unroll
+            for (int q = 0; q < kSamples / kHpEndThreads; ++q) v[q] = view_load(xv, s0 + tid + kHpEndThreads * q);
+            __syncthreads();   // the previous channel's reads are done
+#pragma unroll
+            for (int q = 0; q < kSamples / kHpEndThreads; ++q) xs[hp_word(tid + kHpEndThreads * q)] = v[q];
+            __syncthreads();
+            const int w0 = kHpSub * tid;
+            double x1, x2;
+            if (tid == 0) {
+                x1 = view_load(xv, s0 - 1);
+                x2 = view_load(xv, s0 - 2);
+            } else {
+                x1 = xs[hp_word(w0 - 1)];
+                x2 = xs[hp_word(w0 - 2)];
+            }
+            float xr[kHpSub];
+#pragma unroll
+            for (int i = 0; i < kHpSub; ++i) xr[i] = xs[hp_word(w0 + i)];
+            es[tid] = hp_sub_partial(xr, x1, x2, b0, a1, a2);
+            __syncthreads();
+            const int64_t ci0 = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks + c0;   // the block's first chunk
+            const int c = c0 + tid;
+            if (tid < kHpEndChunks && c < R->n_chunks) {
+                const double* ph = R->phi_sub[1];
+                double d0 = 0.0, d1 = 0.0;
+                for (int j = 0; j < kHpSubPerChunk; ++j) {
+                    const double2 e = es[kHpSubPerChunk * tid + j];
+                    es[kHpSubPerChunk * tid + j] = double2{d0, d1};
+                    const double n0 = e.x + (ph[0] * d0 + ph[1] * d1);
+                    const double n1 = e.y + (ph[2] * d0 + ph[3] * d1);
+                    d0 = n0;
+                    d1 = n1;
                 }
-                __syncthreads();
-                hp_batch_move<false>(y + base, buf, kbase, off, R);
+                zend[2 * (ci0 + tid)] = d0;
+                zend[2 * (ci0 + tid) + 1] = d1;
             }
-            if (live) {
-                const int64_t ci = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks + k;
-                // deviation y - x of the partial response's end state: the
-                // next chunk's starting deviation is this plus phi times this
-                // chunk's starting deviation
-                zend[2 * ci] = y1 - x1;
-                zend[2 * ci + 1] = y2 - x2;
-            }
+            __syncthreads();
+            if (c0 + tid / kHpSubPerChunk < R->n_chunks) sub[kHpSubPerChunk * ci0 + tid] = es[tid];
         }
     }
 }
 
-// Per room: the unforced responses ha, hb of the high-pass over one chunk
-// from the states (y[-1], y[-2]) = (1, 0) and (0, 1), and the phase-major
-// decimation taps; then the initial deviation (y - x at s-1, s-2) of every
-// chunk, one thread per channel, chunk after chunk:
-// init(k + 1) = partial end deviation(k) + phi init(k).
-
+// Deviation at every chunk start, one thread per channel, chunk after chunk:
+// d(0) = 0, d(k + 1) = e(k) + phi d(k).
 __global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ desc, const double* __restrict__ zend,
-                                                      double* __restrict__ init, double* __restrict__ basis,
-                                                      float* __restrict__ dec_taps) {
+                                                      double* __restrict__ init) {
     const DescHeader* H = hdr(desc);
     for (int b = blockIdx.x; b < H->n_rooms; b += gridDim.x) {
         const RoomDesc* R = rooms(desc) + b;
-        const double a1 = R->hp_a1, a2 = R->hp_a2;
-        if (threadIdx.x < 2) {   // lane 0: ha, lane 1: hb
-            double h1 = threadIdx.x == 0 ? 1.0 : 0.0, h2 = threadIdx.x == 0 ? 0.0 : 1.0;
-            double* out = basis + static_cast<int64_t>(b) * kHpBasisStride + threadIdx.x * kHpChunk;
-            for (int i = 0; i < kHpChunk; ++i) {
-                const double h = -a1 * h1 - a2 * h2;
-                out[i] = h;
-                h2 = h1;
-                h1 = h;
-            }
-        }
-        const int rl = static_cast<int>(R->rl);
-        const int half = static_cast<int>(__builtin_ceil(40.5 * rl)) - 1;
-        const int m1 = (half + rl - 1) / rl + 2 * kDecPerThread, len = 2 * m1 + 1;
-        float* taps = dec_taps + static_cast<int64_t>(b) * kDecTapStride;
-        for (int i = threadIdx.x; i < rl * len; i += blockDim.x) {
-            const int q = i / len, m = i % len - m1;
-            const int u = m * rl + q;
-            float v = 0.0f;
-            if (u >= -half && u <= half) {   // P(u / r_l) in FP64, then rounded
-                const double xv = static_cast<double>(u) / rl;
-                double sp, cp, sw, cw;
-                sincospi_d(xv, &sp, &cp);
-                sincospi_d(2.0 * xv / 81.0, &sw, &cw);
-                const double sinc = u == 0 ? 1.0 : sp / (3.141592653589793 * xv);
-                v = static_cast<float>(sinc * 0.5 * (1.0 + cw));
-            }
-            taps[i] = v;
-        }
         const double p0 = R->phi[0], p1 = R->phi[1], p2 = R->phi[2], p3 = R->phi[3];
         for (int local = threadIdx.x; local < R->n_src * R->n_mic; local += blockDim.x) {
             const int64_t c0 = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks;
@@ -1949,123 +1934,261 @@ __global__ void __launch_bounds__(64) hp_carry_kernel(const void* __restrict__ d
 }
 
 
-// Decimation by r_l (Sec. II): out[n] = sum_j x[j] P((n r_l - j) / r_l), the
-// 81-tap Hann-windowed sinc in units of fs.  x is the high-passed signal: the
-// partial chunk responses y0 plus, per chunk k >= 1, init(k) . (ha, hb), added
-// while the tile's input span is staged into LDS (zero outside [0, T_l)).  One
-// block per (tile of kDecOut outputs, room, channel); each thread R
-// consecutive outputs.  With w = r r_l - u, output r reads span[R tid r_l +
-// half + w] with tap k[r r_l - w]: for fixed w every output reads the same
-// input.  The walk goes phase by phase (w mod r_l), R steps at a time: R
-// inputs from LDS and the 2R - 1 taps, consecutive in the phase-major table
-// (uniform: one wide scalar load), per R x R FMAs.
-__global__ void __launch_bounds__(kDecThreads) decimate_kernel(const void* __restrict__ desc,
-                                                               const float* __restrict__ y0,
-                                                               const double* __restrict__ init,
-                                                               const double* __restrict__ basis,
-                                                               const float* __restrict__ dec_taps,
-                                                               float* __restrict__ out) {
-    constexpr int NR = kDecPerThread, UNR = 4, kQ = kHpChunk / kDecThreads;
-    static_assert(kHpChunk == 256 && kQ * kDecThreads == kHpChunk, "staging by chunks of 256");
-    extern __shared__ float span[];
+// Decimation by r_l (Sec. II): out[n] = sum_j y[j] P((n r_l - j) / r_l), the
+// 81-tap Hann-windowed sinc in units of fs (2 half + 1 taps, half = ceil(40.5
+// r_l) - 1), y the high-passed intermediate signal (zero outside [0, T_l)).
+// A block of 256 outputs is a 16 x 16 tile D[i][b] = out[n0 + 16 b + i] =
+// sum_q W[i][q] Y[q][b] with Y[q][b] = y[(n0 + 16 b) r_l - half - pad + q] and
+// W[i][q] = k[i r_l + half + pad - q] (zero outside |u| <= half): a Toeplitz
+// product with the same W for every block, on the matrix cores
+// (v_mfma_f32_16x16x32_f16; pad makes half + pad a multiple of 32, so that
+// every tile's span starts on a sub-chunk boundary and every 8-element operand
+// on a 16-byte boundary).  Operands are fp16 pairs hi + lo (the inputs scaled
+// by a power of two per tile so that the largest is near 2^14), products
+// hi*hi + hi*lo + lo*hi accumulated in FP32.
+
+__host__ __device__ constexpr int dm_half(int rl) { return (81 * rl + 1) / 2 - 1; }   // ceil(40.5 r_l) - 1
+__host__ __device__ constexpr int dm_pad(int rl) { return (32 - dm_half(rl) % 32) % 32; }
+__host__ __device__ constexpr int dm_steps(int rl) {
+    return (dm_pad(rl) + 15 * rl + 2 * dm_half(rl) + 1 + 31) / 32;
+}
+__host__ __device__ constexpr bool dm_steps_fit() {
+    for (int rl = 1; rl <= kMaxRl; ++rl)
+        if (dm_steps(rl) > kDmMaxSteps) return false;
+    return true;
+}
+static_assert(dm_steps_fit(), "fragment table too small for an r_l");
+
+// Window element e sits in word e + 4 (e / 32): four pad words after every 32
+// elements spread the 16 columns of an operand read (16 r_l elements apart)
+// over the LDS banks; pairs, runs of 8 and sub-chunks stay inside one run of
+// 32 (a sub-chunk is words 36 g .. 36 g + 31).
+__device__ __forceinline__ int dm_word(int e) { return e + 4 * (e >> 5); }
+__host__ __device__ constexpr int dm_span(int rl) { return (kDmOut - 1) * rl + 2 * dm_half(rl) + 1 + dm_pad(rl); }
+// A tile stages the window from the start of the chunk holding its span's
+// first sample: at most kHpChunk - kHpSub samples before the span, the span,
+// the rest of its last sub-chunk and one sub-chunk of zeros (operand reads
+// end at most 31 elements past the span).
+__host__ __device__ constexpr int dm_window(int rl) { return (kHpChunk - kHpSub) + dm_span(rl) + 2 * kHpSub; }
+// (at least the four waves' partial tiles: 16 x 256 floats)
+__host__ __device__ constexpr int dm_lds_words(int rl) {
+    return dm_window(rl) + 4 * ((dm_window(rl) + 31) / 32) > 16 * 256 ? dm_window(rl) + 4 * ((dm_window(rl) + 31) / 32)
+                                                                        : 16 * 256;
+}
+
+// The W fragments of every r_l the plan uses: workgroup (r_l - 1, step), lane l
+// (row i = l mod 16, columns 8 (l / 16) .. + 7 of each step); P(u / r_l) in
+// FP64, rounded to FP32, then split into fp16 hi and lo.
+__global__ void __launch_bounds__(64) dec_frag_kernel(const void* __restrict__ desc, uint32_t* __restrict__ frag) {
     const DescHeader* H = hdr(desc);
-    const int tid = threadIdx.x;
+    const int rl = blockIdx.x + 1, st = blockIdx.y;
+    __shared__ int used;
+    if (threadIdx.x == 0) used = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < H->n_rooms; b += blockDim.x)
+        if (static_cast<int>(rooms(desc)[b].rl) == rl) used = 1;
+    __syncthreads();
+    const int half = dm_half(rl), pad = dm_pad(rl);
+    if (!used || st >= dm_steps(rl)) return;
+    const int l = threadIdx.x, i = l % 16;
+    uint32_t* f = frag + static_cast<int64_t>(rl - 1) * kDmFragWords;
+    {
+        uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+        for (int e = 0; e < 8; ++e) {
+            const int q = 32 * st + 8 * (l / 16) + e;
+            const int u = i * rl + half + pad - q;
+            float c = 0.0f;
+            if (u >= -half && u <= half) {
+                const double xv = static_cast<double>(u) / rl;
+                double sp, cp, sw, cw;
+                sincospi_d(xv, &sp, &cp);
+                sincospi_d(2.0 * xv / 81.0, &sw, &cw);
+                const double sinc = u == 0 ? 1.0 : sp / (3.141592653589793 * xv);
+                c = static_cast<float>(sinc * 0.5 * (1.0 + cw));
+            }
+            const _Float16 h = static_cast<_Float16>(c);
+            const _Float16 o = static_cast<_Float16>(c - static_cast<float>(h));
+            hw[e / 2] |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h)) << (16 * (e & 1));
+            lw[e / 2] |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, o)) << (16 * (e & 1));
+        }
+        for (int w = 0; w < 4; ++w) {
+            f[(st * 2 + 0) * 256 + 4 * l + w] = hw[w];
+            f[(st * 2 + 1) * 256 + 4 * l + w] = lw[w];
+        }
+    }
+}
+
+// One workgroup per (tile of kDmOut outputs, room, channel).  Staging: the
+// window from the start of chunk k_first (the chunk holding the span's first
+// sample) is loaded coalesced into LDS; thread t then takes sub-chunks t, t +
+// 256, ... (32 samples each), starts at deviation p_j + phi_sub[j] d(k) with
+// its input history from memory, and runs the recurrence over its samples,
+// writing y (0 outside [0, T_l)) over them.  The span is scaled and converted
+// in place to fp16 pairs: elements (2p, 2p+1) become word 2p = their hi
+// halves, word 2p+1 = their lo halves.  Products: the K steps are dealt to
+// the four waves in turn; a wave applies each filter fragment it loads to all
+// four 256-output blocks (four independent accumulators), and the partial
+// tiles are summed through LDS in wave order.
+__global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu(3))) decimate_mfma_kernel(const void* __restrict__ desc,
+                                                                   const float* __restrict__ x,
+                                                                   const double* __restrict__ init,
+                                                                   const double2* __restrict__ sub,
+                                                                   const uint32_t* __restrict__ frag,
+                                                                   float* __restrict__ out) {
+    extern __shared__ u32x4 span_v[];
+    float* span = reinterpret_cast<float*>(span_v);
+    __shared__ int s_max;   // largest |y| of the tile's span, as float bits
+    static_assert(kHpSub == 32 && kDmBlocks * 64 == kDmThreads, "one wave per block");
+    constexpr int kLoads = 32;   // window samples per thread in flight
+    const DescHeader* H = hdr(desc);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, grp = lane >> 4;
     for (int b = blockIdx.y; b < H->n_rooms; b += gridDim.y) {
         const RoomDesc* R = rooms(desc) + b;
         const int rl = static_cast<int>(R->rl);
-        const int half = static_cast<int>(__builtin_ceil(40.5 * rl)) - 1;
-        const int m1 = (half + rl - 1) / rl + 2 * NR, len = 2 * m1 + 1;
-        const float* taps = dec_taps + static_cast<int64_t>(b) * kDecTapStride;
-        const double* ha = basis + static_cast<int64_t>(b) * kHpBasisStride;
-        const double* hb = ha + kHpChunk;
-        double hav[kQ], hbv[kQ];   // the thread's basis values (offsets tid + 64 q)
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            hav[q] = ha[tid + kDecThreads * q];
-            hbv[q] = hb[tid + kDecThreads * q];
-        }
-        const int n_tiles = (R->T_out + kDecOut - 1) / kDecOut;
+        const int half = dm_half(rl), pad = dm_pad(rl), steps = dm_steps(rl), span_len = dm_span(rl);
+        const double b0 = R->hp_b0, a1 = R->hp_a1, a2 = R->hp_a2;
+        const int T = R->T;
+        const uint32_t* fr = frag + static_cast<int64_t>(rl - 1) * kDmFragWords;
+        const int n_tiles = (R->T_out + kDmOut - 1) / kDmOut;
         for (int local = blockIdx.z; local < R->n_src * R->n_mic; local += gridDim.z) {
-            const float* xc = y0 + R->out_off + static_cast<int64_t>(local) * R->T;
-            const double* ic = init + 2 * (R->chunk0 + static_cast<int64_t>(local) * R->n_chunks);
+            const __amdgpu_buffer_rsrc_t xv = buffer_view(x + R->out_off + static_cast<int64_t>(local) * T, T);
+            const int64_t ci0 = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks;
             for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-                __syncthreads();
-                const int n0 = tile * kDecOut;
-                const int64_t jb = static_cast<int64_t>(n0) * rl - half;   // input index of span[0]
-                const int span_len = (kDecOut - 1) * rl + 2 * half + 1;
-                // staged by high-pass chunks: thread tid takes offsets o = tid +
-                // 64 q of every chunk k the span touches, so its basis values
-                // are loaded once and the chunk's carried state is uniform;
-                // UNR chunks' loads in flight together
-                const int64_t k_first = jb >> 8, k_last = (jb + span_len - 1) >> 8;   // kHpChunk = 256
-                for (int64_t k0 = k_first; k0 <= k_last; k0 += UNR) {
-                    float xv[UNR][kQ];
+                const int n0 = tile * kDmOut;
+                const int64_t jb = static_cast<int64_t>(n0) * rl - half - pad;   // span start (multiple of 32)
+                const int64_t kf = jb >> 8;                                      // k_first (kHpChunk = 256)
+                const int64_t wb = kf * kHpChunk;                                // window start
+                const int woff = static_cast<int>(jb - wb);
+                const int n_sub = (woff + span_len + kHpSub - 1) / kHpSub;
+                const int n_el = n_sub * kHpSub;
+                __syncthreads();   // the previous tile's reads are done
+                if (tid == 0) s_max = 0;
+                // coalesced load of the window
+                for (int w0 = 0; w0 < n_el; w0 += kLoads * kDmThreads) {
+                    float v[kLoads];
 #pragma unroll
-                    for (int u = 0; u < UNR; ++u)
+                    for (int u = 0; u < kLoads; ++u) {
+                        const int w = w0 + tid + kDmThreads * u;
+                        v[u] = w < n_el ? view_load(xv, wb + w) : 0.0f;
+                    }
 #pragma unroll
-                        for (int q = 0; q < kQ; ++q) {
-                            const int64_t j = (k0 + u) * kHpChunk + tid + kDecThreads * q;
-                            xv[u][q] = (k0 + u <= k_last && j >= 0 && j < R->T) ? xc[j] : 0.0f;
-                        }
-#pragma unroll
-                    for (int u = 0; u < UNR; ++u) {
-                        const int64_t k = k0 + u;
-                        if (k > k_last) break;
-                        const bool carry = k > 0 && k * kHpChunk < R->T;
-                        const double c0 = carry ? ic[2 * k] : 0.0, c1 = carry ? ic[2 * k + 1] : 0.0;
-#pragma unroll
-                        for (int q = 0; q < kQ; ++q) {
-                            const int64_t j = k * kHpChunk + tid + kDecThreads * q;
-                            const int64_t i = j - jb;
-                            if (i < 0 || i >= span_len) continue;
-                            double v = 0.0;
-                            if (j >= 0 && j < R->T) {
-                                v = xv[u][q];
-                                if (carry) v += c0 * hav[q] + c1 * hbv[q];
-                            }
-                            span[i] = static_cast<float>(v);
-                        }
+                    for (int u = 0; u < kLoads; ++u) {
+                        const int w = w0 + tid + kDmThreads * u;
+                        if (w < n_el) span[dm_word(w)] = v[u];
                     }
                 }
+                for (int w = n_el + tid; w < n_el + kHpSub; w += kDmThreads) span[dm_word(w)] = 0.0f;
                 __syncthreads();
-                float acc[NR];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) acc[r] = 0.0f;
-                const int sbase = NR * tid * rl + half;
-                const int w_hi = (NR - 1) * rl + half;   // w runs over [-half, w_hi]
-                for (int p = 0; p < rl; ++p) {
-                    // w = a r_l + p; the tap of output r, k[(r - a) r_l - p], is row
-                    // q = (r_l - p) mod r_l, column m = r - a - (p > 0) of the table
-                    int w = -half + (p + half) % rl;
-                    int a = (w - p) / rl;
-                    const int sh = p > 0 ? 1 : 0;
-                    const float* tq = taps + ((rl - p) % rl) * len + m1;   // tq[m]
-                    for (; w + (NR - 1) * rl <= w_hi; w += NR * rl, a += NR) {
-                        // inputs at w + s r_l (s < NR); output r takes the tap at
-                        // column (r - s) - a - sh = m0 + (r - s + NR - 1)
-                        const int m0 = -(NR - 1) - a - sh;
-                        float xs[NR], tt[2 * NR - 1];
-#pragma unroll
-                        for (int s2 = 0; s2 < NR; ++s2) xs[s2] = span[sbase + w + s2 * rl];
-#pragma unroll
-                        for (int d = 0; d < 2 * NR - 1; ++d) tt[d] = tq[m0 + d];
-#pragma unroll
-                        for (int s2 = 0; s2 < NR; ++s2)
-#pragma unroll
-                            for (int r = 0; r < NR; ++r) acc[r] = __builtin_fmaf(tt[r - s2 + NR - 1], xs[s2], acc[r]);
+                float vmax = 0.0f;
+                for (int g = tid; g < n_sub; g += kDmThreads) {
+                    const int64_t s = wb + static_cast<int64_t>(kHpSub) * g;   // first sample of the sub-chunk
+                    const int64_t k = kf + g / kHpSubPerChunk;
+                    const int j = g % kHpSubPerChunk;
+                    double x1 = view_load(xv, s - 1), x2 = view_load(xv, s - 2);
+                    double d0 = 0.0, d1 = 0.0;
+                    if (k >= 0 && k < R->n_chunks) {
+                        const double2 pj = sub[kHpSubPerChunk * (ci0 + k) + j];
+                        d0 = pj.x;
+                        d1 = pj.y;
+                        if (k > 0) {
+                            const double i0 = init[2 * (ci0 + k)], i1 = init[2 * (ci0 + k) + 1];
+                            const double* ph = R->phi_sub[j];
+                            d0 += ph[0] * i0 + ph[1] * i1;
+                            d1 += ph[2] * i0 + ph[3] * i1;
+                        }
                     }
-                    for (; w <= w_hi; w += rl, ++a) {   // the phase's last steps
-                        const float xv = span[sbase + w];
+                    float xr[kHpSub];
+                    const f32x4* src = reinterpret_cast<const f32x4*>(span + dm_word(kHpSub * g));
 #pragma unroll
-                        for (int r = 0; r < NR; ++r) acc[r] = __builtin_fmaf(tq[r - a - sh], xv, acc[r]);
+                    for (int i = 0; i < kHpSub / 4; ++i) {
+                        const f32x4 q = src[i];
+                        xr[4 * i] = q.x;
+                        xr[4 * i + 1] = q.y;
+                        xr[4 * i + 2] = q.z;
+                        xr[4 * i + 3] = q.w;
                     }
+                    double y1 = x1 + d0, y2 = x2 + d1;
+                    const bool inside = s >= 0 && s + kHpSub <= T;
+#pragma unroll
+                    for (int i = 0; i < kHpSub; ++i) {
+                        const float yv = static_cast<float>(hp_step(xr[i], x1, x2, y1, y2, b0, a1, a2));
+                        xr[i] = inside || (s + i >= 0 && s + i < T) ? yv : 0.0f;
+                    }
+                    if (kHpSub * g >= woff)
+#pragma unroll
+                        for (int i = 0; i < kHpSub; ++i) vmax = fmaxf(vmax, fabsf(xr[i]));
+                    f32x4* dst = reinterpret_cast<f32x4*>(span + dm_word(kHpSub * g));
+#pragma unroll
+                    for (int i = 0; i < kHpSub / 4; ++i) dst[i] = f32x4{xr[4 * i], xr[4 * i + 1], xr[4 * i + 2], xr[4 * i + 3]};
                 }
+                atomicMax(&s_max, __float_as_int(vmax));
+                // the wave's first filter fragments load during the conversion
+                int fl = lane;
+                asm volatile("" : "+v"(fl));
+                u32x4 ah = u32x4{0u, 0u, 0u, 0u}, al = ah;
+                if (wave < steps) {
+                    ah = *reinterpret_cast<const u32x4*>(fr + (wave * 2 + 0) * 256 + 4 * fl);
+                    al = *reinterpret_cast<const u32x4*>(fr + (wave * 2 + 1) * 256 + 4 * fl);
+                }
+                __syncthreads();
+                // scale: the largest input to ~2^14 (fp16 keeps the lo halves normal)
+                const float mx = __int_as_float(s_max);
+                const int ex = mx > 0.0f ? max(-100, (__float_as_int(mx) >> 23) - 127) : 0;
+                const float sc = __int_as_float((127 + 14 - ex) << 23), inv_sc = __int_as_float((127 - 14 + ex) << 23);
+                for (int p = woff / 2 + tid; p < (n_el + kHpSub) / 2; p += kDmThreads) {
+                    float* w = span + dm_word(2 * p);
+                    const float a = w[0] * sc, c = w[1] * sc;
+                    const uint32_t hw = pack_f16(a, c);
+                    const uint32_t lw = pack_f16(a - f16_lo_of(hw), c - f16_hi_of(hw));
+                    reinterpret_cast<uint32_t*>(w)[0] = hw;
+                    reinterpret_cast<uint32_t*>(w)[1] = lw;
+                }
+                __syncthreads();
+                // steps wave, wave + 4, ...: column col of block blk starts at
+                // window element woff + (256 blk + 16 col) r_l
+                f32x4 acc[kDmBlocks];
+#pragma unroll
+                for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                const int cb = woff + 16 * col * rl + 8 * grp;
+                for (int st = wave; st < steps; st += kDmBlocks) {
+                    u32x4 ahn = ah, aln = al;
+                    if (st + kDmBlocks < steps) {
+                        ahn = *reinterpret_cast<const u32x4*>(fr + ((st + kDmBlocks) * 2 + 0) * 256 + 4 * fl);
+                        aln = *reinterpret_cast<const u32x4*>(fr + ((st + kDmBlocks) * 2 + 1) * 256 + 4 * fl);
+                    }
+                    u32x4 bh[kDmBlocks], bl[kDmBlocks];
+#pragma unroll
+                    for (int blk = 0; blk < kDmBlocks; ++blk) {
+                        const uint32_t* w = reinterpret_cast<const uint32_t*>(span) + dm_word(cb + 256 * blk * rl + 32 * st);
+                        const u32x4 w0 = *reinterpret_cast<const u32x4*>(w);
+                        const u32x4 w1 = *reinterpret_cast<const u32x4*>(w + 4);
+                        bh[blk] = u32x4{w0[0], w0[2], w1[0], w1[2]};
+                        bl[blk] = u32x4{w0[1], w0[3], w1[1], w1[3]};
+                    }
+#pragma unroll
+                    for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = mfma_16x16x32(ah, bh[blk], acc[blk]);
+#pragma unroll
+                    for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = mfma_16x16x32(ah, bl[blk], acc[blk]);
+#pragma unroll
+                    for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = mfma_16x16x32(al, bh[blk], acc[blk]);
+                    ah = ahn;
+                    al = aln;
+                }
+                __syncthreads();   // every wave is done with the span: it now holds the partial tiles
+                f32x4* part = reinterpret_cast<f32x4*>(span);
+#pragma unroll
+                for (int blk = 0; blk < kDmBlocks; ++blk) part[(wave * kDmBlocks + blk) * 64 + lane] = acc[blk];
+                __syncthreads();
+                f32x4 sum = part[wave * 64 + lane];
+#pragma unroll
+                for (int v = 1; v < kDmBlocks; ++v) sum += part[(v * kDmBlocks + wave) * 64 + lane];
+                // lane: outputs n .. n + 3 (rows 4 grp .. 4 grp + 3 of column col of block wave)
                 float* o = out + R->out2_off + static_cast<int64_t>(local) * R->T_out;
+                const int n = n0 + 256 * wave + 16 * col + 4 * grp;
 #pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    const int n = n0 + NR * tid + r;
-                    if (n < R->T_out) o[n] = acc[r];
-                }
+                for (int i = 0; i < 4; ++i)
+                    if (n + i < R->T_out) o[n + i] = sum[i] * inv_sc;
             }
         }
     }
@@ -2525,12 +2648,6 @@ extern "C" int framrir_early(const framrir_plan* plan, const void* desc_dev, con
     return check_launch("early_kernel");
 }
 
-// LDS floats of decimate_kernel for a given r_l (the input span).
-int dec_lds_floats(int rl) {
-    const int half = static_cast<int>(std::ceil(40.5 * rl)) - 1;
-    return (kDecOut - 1) * rl + 2 * half + 1;
-}
-
 extern "C" int framrir_multirate_filter(const framrir_plan* plan, const void* desc_dev, float* inter_dev,
                                         float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
@@ -2562,23 +2679,24 @@ extern "C" int framrir_multirate_filter(const framrir_plan* plan, const void* de
                        static_cast<long long>(plan->ws_mr_bytes));
     int rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    float* filt = inter_dev + H.mr_floats;
     double* zend = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + plan->ws_zend_off);
     double* init = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + plan->ws_init_off);
     const unsigned gy = static_cast<unsigned>(std::min(H.n_rooms, 65535));
     const unsigned gz = static_cast<unsigned>(std::min(H.max_room_chan, 65535));
-    const unsigned gc = static_cast<unsigned>((H.max_chunks + 63) / 64);
-    hipLaunchKernelGGL(hp_zero_state_kernel, dim3(gc, gy, gz), dim3(64), 0, st, desc_dev, inter_dev, filt, zend);
-    if ((rc = check_launch("hp_zero_state_kernel"))) return rc;
-    double* basis = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + plan->ws_basis_off);
-    float* dec_taps = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + plan->ws_taps_off);
-    hipLaunchKernelGGL(hp_carry_kernel, dim3(gy), dim3(64), 0, st, desc_dev, zend, init, basis, dec_taps);
+    const unsigned gc = static_cast<unsigned>((H.max_chunks + kHpEndChunks - 1) / kHpEndChunks);
+    double2* sub = reinterpret_cast<double2*>(static_cast<char*>(ws_dev) + plan->ws_sub_off);
+    hipLaunchKernelGGL(hp_chunk_end_kernel, dim3(gc, gy, gz), dim3(kHpEndThreads), 0, st, desc_dev, inter_dev, zend, sub);
+    if ((rc = check_launch("hp_chunk_end_kernel"))) return rc;
+    hipLaunchKernelGGL(hp_carry_kernel, dim3(gy), dim3(64), 0, st, desc_dev, zend, init);
     if ((rc = check_launch("hp_carry_kernel"))) return rc;
-    const int lds = 4 * dec_lds_floats(H.max_rl);
-    if (int rc2 = allow_lds<decimate_kernel>()) return rc2;
-    hipLaunchKernelGGL(decimate_kernel, dim3(static_cast<unsigned>(std::min(H.max_out_tiles, 65535)), gy, gz),
-                       dim3(kDecThreads), lds, st, desc_dev, filt, init, basis, dec_taps, out_dev);
-    return check_launch("decimate_kernel");
+    uint32_t* frag = reinterpret_cast<uint32_t*>(static_cast<char*>(ws_dev) + plan->ws_taps_off);
+    hipLaunchKernelGGL(dec_frag_kernel, dim3(kMaxRl, kDmMaxSteps), dim3(64), 0, st, desc_dev, frag);
+    if ((rc = check_launch("dec_frag_kernel"))) return rc;
+    const int lds = 4 * dm_lds_words(H.max_rl);
+    if (int rc2 = allow_lds<decimate_mfma_kernel, 4 * dm_lds_words(kMaxRl)>()) return rc2;
+    hipLaunchKernelGGL(decimate_mfma_kernel, dim3(static_cast<unsigned>(std::min(H.max_out_tiles, 65535)), gy, gz),
+                       dim3(kDmThreads), lds, st, desc_dev, inter_dev, init, sub, frag, out_dev);
+    return check_launch("decimate_mfma_kernel");
 }
 
 extern "C" int framrir_workspace_init(void* ws_dev, size_t ws_bytes, void* stream) {

@@ -280,25 +280,30 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
             R.hp_b0 = 1.0 / norm;
             R.hp_a1 = 2.0 * (k * k - 1.0) / norm;
             R.hp_a2 = (1.0 - std::sqrt(2.0) * k + k * k) / norm;
-            // phi = M^kHpChunk, M = [[-a1, -a2], [1, 0]] maps (y[n-1], y[n-2])
-            // of the unforced recurrence to (y[n], y[n-1])
-            double m[4] = {-R.hp_a1, -R.hp_a2, 1.0, 0.0}, acc[4] = {1.0, 0.0, 0.0, 1.0};
-            for (int e = kHpChunk; e > 0; e >>= 1) {
-                double t[4];
-                if (e & 1) {
-                    t[0] = acc[0] * m[0] + acc[1] * m[2];
-                    t[1] = acc[0] * m[1] + acc[1] * m[3];
-                    t[2] = acc[2] * m[0] + acc[3] * m[2];
-                    t[3] = acc[2] * m[1] + acc[3] * m[3];
-                    std::memcpy(acc, t, sizeof(t));
+            // phi = M^kHpChunk and phi_sub[j] = M^(j kHpSub), M = [[-a1, -a2], [1, 0]]
+            // mapping (y[n-1], y[n-2]) of the unforced recurrence to (y[n], y[n-1])
+            const auto mat_pow = [&](int n, double* out) {
+                double m[4] = {-R.hp_a1, -R.hp_a2, 1.0, 0.0}, acc[4] = {1.0, 0.0, 0.0, 1.0};
+                for (int e = n; e > 0; e >>= 1) {
+                    double t[4];
+                    if (e & 1) {
+                        t[0] = acc[0] * m[0] + acc[1] * m[2];
+                        t[1] = acc[0] * m[1] + acc[1] * m[3];
+                        t[2] = acc[2] * m[0] + acc[3] * m[2];
+                        t[3] = acc[2] * m[1] + acc[3] * m[3];
+                        std::memcpy(acc, t, sizeof(t));
+                    }
+                    t[0] = m[0] * m[0] + m[1] * m[2];
+                    t[1] = m[0] * m[1] + m[1] * m[3];
+                    t[2] = m[2] * m[0] + m[3] * m[2];
+                    t[3] = m[2] * m[1] + m[3] * m[3];
+                    std::memcpy(m, t, sizeof(t));
                 }
-                t[0] = m[0] * m[0] + m[1] * m[2];
-                t[1] = m[0] * m[1] + m[1] * m[3];
-                t[2] = m[2] * m[0] + m[3] * m[2];
-                t[3] = m[2] * m[1] + m[3] * m[3];
-                std::memcpy(m, t, sizeof(t));
-            }
-            std::memcpy(R.phi, acc, sizeof(acc));
+                std::memcpy(out, acc, sizeof(acc));
+            };
+            mat_pow(kHpChunk, R.phi);
+            static_assert(kHpChunk == 8 * kHpSub, "eight sub-chunks per chunk");
+            for (int j = 0; j < 8; ++j) mat_pow(j * kHpSub, R.phi_sub[j]);
             R.n_chunks = (T_r + kHpChunk - 1) / kHpChunk;
             R.chunk0 = chunk_row;
         }
@@ -367,7 +372,7 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
             out2_off += static_cast<int64_t>(n_chan_room) * T;
             chunk_row += static_cast<int64_t>(n_chan_room) * R.n_chunks;
             max_chunks = std::max(max_chunks, R.n_chunks);
-            max_out_tiles = std::max(max_out_tiles, (T + kDecOut - 1) / kDecOut);
+            max_out_tiles = std::max(max_out_tiles, (T + kDmOut - 1) / kDmOut);
             max_rl = std::max(max_rl, rl);
         }
         early_off += static_cast<int64_t>(n_chan_room) * (R.early_pre + R.early_post + 1);
@@ -498,13 +503,15 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     plan->ws_part_off = plan->ws_bytes;
     plan->ws_bwd_bytes = plan->ws_part_off + align(static_cast<int64_t>(sizeof(float)) * kPartialStride * it.size());
     // multi-rate: per high-pass chunk the end deviation y - x of its partial
-    // response (2 doubles) and its initial deviation (2 doubles)
+    // response (2 doubles) and its initial deviation (2 doubles), per
+    // sub-chunk the deviation of the chunk's partial response at its start (2
+    // doubles), then the decimation fragments
     plan->ws_zend_off = align(plan->ws_bytes);
     plan->ws_init_off = align(plan->ws_zend_off + 16 * chunk_row);
-    plan->ws_basis_off = align(plan->ws_init_off + 16 * chunk_row);
-    plan->ws_taps_off = align(plan->ws_basis_off + static_cast<int64_t>(sizeof(double)) * kHpBasisStride * n_rooms);
+    plan->ws_sub_off = align(plan->ws_init_off + 16 * chunk_row);
+    plan->ws_taps_off = align(plan->ws_sub_off + 16 * 8 * chunk_row);
     plan->ws_mr_bytes =
-        multirate ? align(plan->ws_taps_off + static_cast<int64_t>(sizeof(float)) * kDecTapStride * n_rooms) : 0;
+        multirate ? align(plan->ws_taps_off + static_cast<int64_t>(sizeof(uint32_t)) * kDmFragWords * kMaxRl) : 0;
     int32_t grid = launch.grid_wgs;
     if (grid == 0) {
         const int static_lds = launch.render_path == 1 ? kMomStaticLds : render_static_lds(launch.wg_threads);

@@ -60,9 +60,10 @@ struct framrir_plan {
     int64_t ws_scale_off = 0, ws_bucket_off = 0, ws_row0_off = 0, ws_room_off = 0, ws_rows_off = 0,
             ws_part_off = 0;
     // multi-rate workspace (ws_mr_bytes): the render workspace, then per
-    // high-pass chunk its partial end deviation and its initial deviation, per room the
-    // high-pass unforced responses over a chunk and the decimation taps
-    int64_t ws_zend_off = 0, ws_init_off = 0, ws_basis_off = 0, ws_taps_off = 0, ws_mr_bytes = 0;
+    // high-pass chunk its partial end deviation and its initial deviation, per
+    // sub-chunk the chunk's partial deviation at its start, and per r_l the
+    // decimation filter's matrix-core fragments
+    int64_t ws_zend_off = 0, ws_init_off = 0, ws_sub_off = 0, ws_taps_off = 0, ws_mr_bytes = 0;
 };
 
 int fr_fail(int code, const char* fmt, ...);

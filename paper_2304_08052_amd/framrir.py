@@ -448,12 +448,12 @@ class Plan:
                           stream=None, desc=None):
         """framrir_forward_multirate: draws, the render at r_l fs on the high-rate
         grid, the 80 Hz high-pass and the decimation to fs.  Returns
-        (out [out_floats], table, inter [2 mr_floats]: the intermediate signal
-        at r_l fs, then the high-pass scratch)."""
+        (out [out_floats], table, inter [mr_floats]: the intermediate signal
+        at r_l fs)."""
         import torch
         table = self.empty_table() if table is None else table
         out = self.empty_out() if out is None else out
-        inter = torch.empty(2 * self.info.mr_floats, dtype=torch.float32, device=self.device) if inter is None \
+        inter = torch.empty(self.info.mr_floats, dtype=torch.float32, device=self.device) if inter is None \
             else inter
         ws = torch.zeros(self.info.ws_mr_bytes, dtype=torch.uint8, device=self.device) if ws is None else ws
         mic = self.mic_dev if mic is None else mic
