@@ -2018,6 +2018,29 @@ __global__ void __launch_bounds__(64) dec_frag_kernel(const void* __restrict__ d
     }
 }
 
+// Start state of sub-chunk g of a decimation window: input history x1, x2,
+// the chunk's partial deviation p at the sub-chunk and the chunk's start
+// deviation i (0 before the signal, and for chunk 0).
+struct DmStart {
+    float x1, x2;
+    double2 p, i;
+};
+__device__ __forceinline__ DmStart dm_start_load(__amdgpu_buffer_rsrc_t xv, const double2* __restrict__ sub,
+                                                 const double* __restrict__ init, const RoomDesc* R, int64_t ci0,
+                                                 int64_t kf, int64_t wb, int g, int n_sub) {
+    DmStart r{0.0f, 0.0f, double2{0.0, 0.0}, double2{0.0, 0.0}};
+    if (g >= n_sub) return r;
+    const int64_t s = wb + static_cast<int64_t>(kHpSub) * g;
+    const int64_t k = kf + g / kHpSubPerChunk;
+    r.x1 = view_load(xv, s - 1);
+    r.x2 = view_load(xv, s - 2);
+    if (k >= 0 && k < R->n_chunks) {
+        r.p = sub[kHpSubPerChunk * (ci0 + k) + g % kHpSubPerChunk];
+        if (k > 0) r.i = reinterpret_cast<const double2*>(init)[ci0 + k];
+    }
+    return r;
+}
+
 // One workgroup per (tile of kDmOut outputs, room, channel).  Staging: the
 // window from the start of chunk k_first (the chunk holding the span's first
 // sample) is loaded coalesced into LDS; thread t then takes sub-chunks t, t +
@@ -2029,7 +2052,7 @@ __global__ void __launch_bounds__(64) dec_frag_kernel(const void* __restrict__ d
 // the four waves in turn; a wave applies each filter fragment it loads to all
 // four 256-output blocks (four independent accumulators), and the partial
 // tiles are summed through LDS in wave order.
-__global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu(3))) decimate_mfma_kernel(const void* __restrict__ desc,
+__global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu(4))) decimate_mfma_kernel(const void* __restrict__ desc,
                                                                    const float* __restrict__ x,
                                                                    const double* __restrict__ init,
                                                                    const double2* __restrict__ sub,
@@ -2039,7 +2062,7 @@ __global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu
     float* span = reinterpret_cast<float*>(span_v);
     __shared__ int s_max;   // largest |y| of the tile's span, as float bits
     static_assert(kHpSub == 32 && kDmBlocks * 64 == kDmThreads, "one wave per block");
-    constexpr int kLoads = 32;   // window samples per thread in flight
+    constexpr int kLoads = 8;   // window samples per thread in flight (4 waves per SIMD without spills)
     const DescHeader* H = hdr(desc);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, grp = lane >> 4;
@@ -2079,25 +2102,17 @@ __global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu
                     }
                 }
                 for (int w = n_el + tid; w < n_el + kHpSub; w += kDmThreads) span[dm_word(w)] = 0.0f;
+                // the first sub-chunk's start state loads while the window lands
+                DmStart ss = dm_start_load(xv, sub, init, R, ci0, kf, wb, tid, n_sub);
                 __syncthreads();
                 float vmax = 0.0f;
                 for (int g = tid; g < n_sub; g += kDmThreads) {
+                    if (g != tid) ss = dm_start_load(xv, sub, init, R, ci0, kf, wb, g, n_sub);
                     const int64_t s = wb + static_cast<int64_t>(kHpSub) * g;   // first sample of the sub-chunk
-                    const int64_t k = kf + g / kHpSubPerChunk;
-                    const int j = g % kHpSubPerChunk;
-                    double x1 = view_load(xv, s - 1), x2 = view_load(xv, s - 2);
-                    double d0 = 0.0, d1 = 0.0;
-                    if (k >= 0 && k < R->n_chunks) {
-                        const double2 pj = sub[kHpSubPerChunk * (ci0 + k) + j];
-                        d0 = pj.x;
-                        d1 = pj.y;
-                        if (k > 0) {
-                            const double i0 = init[2 * (ci0 + k)], i1 = init[2 * (ci0 + k) + 1];
-                            const double* ph = R->phi_sub[j];
-                            d0 += ph[0] * i0 + ph[1] * i1;
-                            d1 += ph[2] * i0 + ph[3] * i1;
-                        }
-                    }
+                    const double* ph = R->phi_sub[g % kHpSubPerChunk];
+                    double x1 = ss.x1, x2 = ss.x2;
+                    const double d0 = ss.p.x + (ph[0] * ss.i.x + ph[1] * ss.i.y);
+                    const double d1 = ss.p.y + (ph[2] * ss.i.x + ph[3] * ss.i.y);
                     float xr[kHpSub];
                     const f32x4* src = reinterpret_cast<const f32x4*>(span + dm_word(kHpSub * g));
 #pragma unroll
@@ -2157,21 +2172,25 @@ __global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu
                         ahn = *reinterpret_cast<const u32x4*>(fr + ((st + kDmBlocks) * 2 + 0) * 256 + 4 * fl);
                         aln = *reinterpret_cast<const u32x4*>(fr + ((st + kDmBlocks) * 2 + 1) * 256 + 4 * fl);
                     }
-                    u32x4 bh[kDmBlocks], bl[kDmBlocks];
 #pragma unroll
-                    for (int blk = 0; blk < kDmBlocks; ++blk) {
-                        const uint32_t* w = reinterpret_cast<const uint32_t*>(span) + dm_word(cb + 256 * blk * rl + 32 * st);
-                        const u32x4 w0 = *reinterpret_cast<const u32x4*>(w);
-                        const u32x4 w1 = *reinterpret_cast<const u32x4*>(w + 4);
-                        bh[blk] = u32x4{w0[0], w0[2], w1[0], w1[2]};
-                        bl[blk] = u32x4{w0[1], w0[3], w1[1], w1[3]};
+                    for (int h = 0; h < kDmBlocks; h += 2) {   // two blocks' operands at a time
+                        u32x4 bh[2], bl[2];
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const uint32_t* w =
+                                reinterpret_cast<const uint32_t*>(span) + dm_word(cb + 256 * (h + q) * rl + 32 * st);
+                            const u32x4 w0 = *reinterpret_cast<const u32x4*>(w);
+                            const u32x4 w1 = *reinterpret_cast<const u32x4*>(w + 4);
+                            bh[q] = u32x4{w0[0], w0[2], w1[0], w1[2]};
+                            bl[q] = u32x4{w0[1], w0[3], w1[1], w1[3]};
+                        }
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) acc[h + q] = mfma_16x16x32(ah, bh[q], acc[h + q]);
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) acc[h + q] = mfma_16x16x32(ah, bl[q], acc[h + q]);
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) acc[h + q] = mfma_16x16x32(al, bh[q], acc[h + q]);
                     }
-#pragma unroll
-                    for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = mfma_16x16x32(ah, bh[blk], acc[blk]);
-#pragma unroll
-                    for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = mfma_16x16x32(ah, bl[blk], acc[blk]);
-#pragma unroll
-                    for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = mfma_16x16x32(al, bh[blk], acc[blk]);
                     ah = ahn;
                     al = aln;
                 }
