@@ -324,12 +324,14 @@ def main():
         copy_probe(args.copy_probe_mb)
 
     # forward step = framrir_forward split in its two launches: draws +
-    # preparation, then the render kernel (timed on its own for the roofline)
-    def fwd_step(ev=None):
-        plan.prepare(table, ws=ws, draw=True)
+    # preparation, then the render kernel (timed on its own for the roofline).
+    # The step without the image table (tab=None: the preparation draws each
+    # row again instead of reading the table back) is timed beside it.
+    def fwd_step(ev=None, tab=table):
+        plan.prepare(tab, ws=ws, draw=True)
         if ev is not None:
             ev[0].record(stream)
-        plan.render_prepared(table, out=out, ws=ws)
+        plan.render_prepared(tab, out=out, ws=ws)
         if ev is not None:
             ev[1].record(stream)
 
@@ -366,7 +368,7 @@ def main():
     render_ms = float(np.median(render_each))
 
     # ---- hipGraph-captured forward step (draw + render): the headline
-    graph_each = None
+    graph_each = graph_notable_each = None
     if not args.no_graph:
         try:
             g = torch.cuda.CUDAGraph()
@@ -382,6 +384,13 @@ def main():
                 g.replay()
             torch.cuda.synchronize()
             graph_each, _ = per_step(g.replay, args.steps)
+            gt = torch.cuda.CUDAGraph()   # the same step without an image table
+            with torch.cuda.graph(gt):
+                fwd_step(tab=None)
+            for _ in range(args.warmup):
+                gt.replay()
+            torch.cuda.synchronize()
+            graph_notable_each, _ = per_step(gt.replay, args.steps)
         except Exception as exc:      # graph capture unavailable: report eager only
             print(f"[bench] graph capture failed: {exc}", file=sys.stderr)
             graph_each = None
@@ -513,6 +522,7 @@ def main():
         "eager_ms_per_step": eager_ms,
         "eager_ms_p10_p50_p90": pct(eager_each),
         "graph_ms_per_step": graph_ms,
+        "graph_without_table_ms_p10_p50_p90": pct(graph_notable_each) if graph_notable_each is not None else None,
         "fwd_bwd_ms_per_step": fb_ms,
         "fwd_bwd_ms_p10_p50_p90": pct(fb_each) if fb_each is not None else None,
         "fwd_bwd_over_fwd": (fb_ms / eager_ms) if fb_ms else None,

@@ -223,7 +223,10 @@ int framrir_render(const framrir_plan* plan, const void* desc_dev, const double*
 
 /* Draw and render in one call (table_dev as for framrir_draw): the draws
  * run inside the preparation kernel (framrir_prepare with draw = 1), then
- * framrir_render_prepared. */
+ * framrir_render_prepared.  table_dev may be NULL: the draws are then not
+ * exported (the preparation draws each row a second time where it would
+ * read the table back), and the output, the workspace's delay-ordered rows
+ * and everything computed from them are the same bit for bit. */
 int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* table_dev,
                     const double* mic_dev, const double* src_dev, const double* r_dev,
                     float* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
@@ -234,8 +237,8 @@ int framrir_forward(const framrir_plan* plan, const void* desc_dev, double* tabl
  * FRAMRIR_NOALLOC_SCRATCH_BYTES (64 MiB) per device, held by every device
  * the library runs on until the process ends (its address is looked up once
  * per device, on the first call with that device current).  Arguments, the
- * table and the outputs as for framrir_forward; the caller still owns the
- * table, positions and output.  The call allocates nothing and enqueues a
+ * table (which may be NULL) and the outputs as for framrir_forward; the
+ * caller still owns the table, positions and output.  The call allocates nothing and enqueues a
  * small kernel that clears the workspace's counters, then the preparation
  * (with the draws) and the render.  Every call on one device shares that
  * device's array, which keeps the last call's contents: calls that overlap on
@@ -265,10 +268,11 @@ int framrir_forward_early(const framrir_plan* plan, const void* desc_dev, double
  * bound on the sum of its pulse amplitudes over the microphones) and a copy
  * of its rows (row 0 at src_dev's position, amplitude r^g precomputed)
  * ordered by delay; with draw != 0 it first draws the rows into table_dev
- * (as framrir_draw).  framrir_render_prepared then renders from the
- * workspace alone (table_dev and src_dev are not read); its workspace must
- * hold the preparation of the same plan, table, positions and r.  Arguments
- * and errors as for framrir_render. */
+ * (as framrir_draw; table_dev may then be NULL, as for framrir_forward).
+ * framrir_render_prepared then renders from the workspace alone (table_dev,
+ * which may be NULL, and src_dev are not read); its workspace must hold the
+ * preparation of the same plan, table, positions and r.  Arguments and
+ * errors as for framrir_render. */
 int framrir_prepare(const framrir_plan* plan, const void* desc_dev, double* table_dev, const double* mic_dev,
                     const double* src_dev, const double* r_dev, int draw, void* ws_dev, size_t ws_bytes,
                     void* stream);

@@ -661,7 +661,9 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
     const double log2r = log2(r);
     const float inv_w = bucket_inv_width(R->T);
     const int n = S->n_img;
-    const double4* trow = reinterpret_cast<const double4*>(table) + S->img_off;
+    // rows read back from the table; none when drawing without one (the
+    // second pass then draws each row again)
+    const double4* trow = table ? reinterpret_cast<const double4*>(table) + S->img_off : nullptr;
     const double4 src_row = make_double4(src[3 * s], src[3 * s + 1], src[3 * s + 2], 0.0);
     // this wave's rows: [w0, w1), in runs of 64
     const int per_wave = (((n + NW - 1) / NW) + 63) & ~63;
@@ -686,8 +688,8 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
             const int i0 = c + lane, i1 = c + 64 + lane;
             const bool valid0 = i0 < w1, valid1 = i1 < w1;
             double4 v0 = make_double4(0.0, 0.0, 0.0, 0.0), v1 = v0;
-            if (valid0) v0 = prep_row<true>(H, S, R, s, i0, table, src, true);
-            if (valid1) v1 = prep_row<true>(H, S, R, s, i1, table, src, true);
+            if (valid0) v0 = prep_row<true>(H, S, R, s, i0, table, src, table != nullptr);
+            if (valid1) v1 = prep_row<true>(H, S, R, s, i1, table, src, table != nullptr);
             count_run(i0, valid0, v0);
             if (c + 64 < w1) count_run(i1, valid1, v1);
         }
@@ -769,7 +771,7 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
     // instruction resolves its colliding lanes in a fixed order, so the
     // layout, and every sum later taken over it, is a function of the input
     // alone.  Rows come back from the table (for DRAW the lane's own stores
-    // of pass 1).
+    // of pass 1), or are drawn again when there is no table.
     double4* dst = reinterpret_cast<double4*>(sorted) + S->img_off;
     for (int c = w0; c < w1; c += 4 * 64) {
         double4 v[4];
@@ -777,7 +779,11 @@ __global__ void __launch_bounds__(kPrepThreads) prep_kernel(const void* __restri
         for (int k = 0; k < 4; ++k) {
             const int i = c + 64 * k + lane;
             v[k] = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (i < w1) v[k] = i == 0 ? src_row : trow[i];
+            if constexpr (DRAW) {
+                if (i < w1) v[k] = trow ? (i == 0 ? src_row : trow[i]) : prep_row<true>(H, S, R, s, i, nullptr, src, false);
+            } else {
+                if (i < w1) v[k] = i == 0 ? src_row : trow[i];
+            }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -2375,9 +2381,12 @@ int launch_render(const framrir_plan* plan, const void* desc_dev, const double* 
     return check_launch("render_kernel");
 }
 
+// table_dev may be NULL where the call does not read it (a forward that
+// draws, the render of prepared rows).
 int check_render_args(const framrir_plan* plan, const void* desc_dev, const double* table_dev, const double* mic_dev,
-                      const double* src_dev, const void* out_dev, void* ws_dev, size_t ws_bytes, int64_t need) {
-    if (!plan || !desc_dev || !table_dev || !mic_dev || !src_dev || !out_dev || !ws_dev)
+                      const double* src_dev, const void* out_dev, void* ws_dev, size_t ws_bytes, int64_t need,
+                      bool table_required = true) {
+    if (!plan || !desc_dev || (table_required && !table_dev) || !mic_dev || !src_dev || !out_dev || !ws_dev)
         return fr_fail(FRAMRIR_E_INVALID_ARG, "NULL argument");
     if (!aligned(desc_dev, 256) || !aligned(table_dev, 32) || !aligned(ws_dev, 256) || !aligned(out_dev, 4))
         return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned buffer");
@@ -2393,8 +2402,9 @@ extern "C" int framrir_prepare(const framrir_plan* plan, const void* desc_dev, d
                                void* ws_dev, size_t ws_bytes, void* stream) {
     if (plan && plan->header.multirate)
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
-    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, table_dev, ws_dev, ws_bytes,
-                               plan ? plan->ws_bytes : 0);
+    // (no output buffer: the workspace stands in for it in the check)
+    int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, ws_dev, ws_dev, ws_bytes,
+                               plan ? plan->ws_bytes : 0, draw == 0);
     if (rc) return rc;
     return launch_prepare(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, ws_dev, static_cast<hipStream_t>(stream),
                           draw != 0);
@@ -2406,7 +2416,7 @@ extern "C" int framrir_render_prepared(const framrir_plan* plan, const void* des
     if (plan && plan->header.multirate)
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: use framrir_forward_multirate");
     int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
-                               plan ? plan->ws_bytes : 0);
+                               plan ? plan->ws_bytes : 0, false);
     if (rc) return rc;
     return launch_render(plan, desc_dev, table_dev, mic_dev, src_dev, r_dev, out_dev, ws_dev,
                          static_cast<hipStream_t>(stream));
@@ -2501,7 +2511,7 @@ extern "C" int framrir_forward_noalloc(const framrir_plan* plan, const void* des
     if (rc) return rc;
     // every argument checked before anything is enqueued
     rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws,
-                           static_cast<size_t>(FRAMRIR_NOALLOC_SCRATCH_BYTES), plan->ws_bytes);
+                           static_cast<size_t>(FRAMRIR_NOALLOC_SCRATCH_BYTES), plan->ws_bytes, false);
     if (rc) return rc;
     // the persistent grid's counters start at zero: cleared by a kernel (not
     // a memset node, so that the call can be captured), every call
@@ -2520,7 +2530,7 @@ extern "C" int framrir_forward_early(const framrir_plan* plan, const void* desc_
         return fr_fail(FRAMRIR_E_UNSUPPORTED, "multi-rate plan: the early windows are taken at the output rate");
     if (!early_dev) return fr_fail(FRAMRIR_E_INVALID_ARG, "early_dev is NULL (use framrir_forward)");
     int rc = check_render_args(plan, desc_dev, table_dev, mic_dev, src_dev, out_dev, ws_dev, ws_bytes,
-                               plan ? plan->ws_bytes : 0);
+                               plan ? plan->ws_bytes : 0, false);
     if (rc) return rc;
     if (!aligned(early_dev, 4)) return fr_fail(FRAMRIR_E_INVALID_ARG, "misaligned early_dev");
     hipStream_t st = static_cast<hipStream_t>(stream);

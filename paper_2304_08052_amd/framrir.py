@@ -310,6 +310,36 @@ class Plan:
         n = self.info.ws_bwd_bytes if backward else self.info.ws_bytes
         return torch.zeros(n, dtype=torch.uint8, device=self.device)
 
+    def _ck(self, t, kind):
+        """Device pointer of t for the C ABI after checking what the call reads
+        or writes through it: dtype, contiguity, at least the plan's element
+        count for that argument, and that it lives on a GPU (a wrong dtype
+        would otherwise be read with the wrong element size)."""
+        if t is None:
+            return None
+        import torch
+        i = self.info
+        dtype, numel = {
+            "desc": (torch.uint8, None), "ws": (torch.uint8, None),
+            "table": (torch.float64, 4 * i.n_img), "aux": (torch.float64, 8 * i.n_img),
+            "words": (torch.int32, 4 * i.n_img),
+            "mic": (torch.float64, 3 * i.n_mic), "src": (torch.float64, 3 * i.n_src), "r": (torch.float64, i.n_rooms),
+            "out": (torch.float32, i.out_floats), "gm": (torch.float32, 3 * i.n_mic),
+            "gs": (torch.float32, 3 * i.n_src),
+            "gr": (torch.float32, i.n_rooms), "inter": (torch.float32, i.mr_floats),
+            "early": (torch.float32, i.early_floats), "start": (torch.int32, i.n_chan)}[kind]
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{kind}: expected a torch tensor, got {type(t).__name__}")
+        if t.dtype != dtype:
+            raise TypeError(f"{kind}: dtype {t.dtype}, the library reads {dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{kind}: tensor is not contiguous")
+        if numel is not None and t.numel() < numel:
+            raise ValueError(f"{kind}: {t.numel()} elements, the plan needs {numel}")
+        if t.device.type != "cuda":
+            raise ValueError(f"{kind}: tensor on {t.device}, the library takes device memory")
+        return ctypes.c_void_p(t.data_ptr())
+
     # ---- device calls ------------------------------------------------------
     # Every device call takes an optional desc: a device copy of another
     # plan's descriptor blob launched with this plan's shapes (see stream.py).
@@ -319,7 +349,8 @@ class Plan:
         aux_t = torch.empty((self.info.n_img, 8), dtype=torch.float64, device=self.device) if aux else None
         w_t = torch.empty((self.info.n_img, 4), dtype=torch.int32, device=self.device) if words else None
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_draw(self._h, _ptr(desc), _ptr(table), _ptr(aux_t), _ptr(w_t), _stream(stream)))
+        _check(lib().framrir_draw(self._h, self._ck(desc, "desc"), self._ck(table, "table"), self._ck(aux_t, "aux"),
+                                  self._ck(w_t, "words"), _stream(stream)))
         return table, aux_t, w_t
 
     def render(self, table, mic=None, src=None, r=None, out=None, ws=None, stream=None, desc=None):
@@ -328,27 +359,31 @@ class Plan:
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_render(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                    _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        _check(lib().framrir_render(self._h, self._ck(desc, "desc"), self._ck(table, "table"), self._ck(mic, "mic"),
+                                    self._ck(src, "src"), self._ck(r, "r"), self._ck(out, "out"), self._ck(ws, "ws"),
+                                    ws.numel(), _stream(stream)))
         return out
 
     def forward(self, table=None, mic=None, src=None, r=None, out=None, ws=None, stream=None, desc=None):
-        table = self.empty_table() if table is None else table
+        """framrir_forward; table=False draws without exporting the table
+        (returned as None)."""
+        table = self.empty_table() if table is None else (None if table is False else table)
         out = self.empty_out() if out is None else out
         ws = self.workspace() if ws is None else ws
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_forward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                     _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        _check(lib().framrir_forward(self._h, self._ck(desc, "desc"), self._ck(table, "table"), self._ck(mic, "mic"),
+                                     self._ck(src, "src"), self._ck(r, "r"), self._ck(out, "out"), self._ck(ws, "ws"),
+                                     ws.numel(), _stream(stream)))
         return out, table
 
     def forward_early(self, table=None, mic=None, src=None, r=None, out=None, early=None, start=None, ws=None,
                       stream=None, desc=None):
         """framrir_forward_early: the forward and the Eq. 9 windows from the
-        same pass; returns (out, table, early, start)."""
+        same pass; returns (out, table, early, start) (table=False: no table)."""
         import torch
-        table = self.empty_table() if table is None else table
+        table = self.empty_table() if table is None else (None if table is False else table)
         out = self.empty_out() if out is None else out
         early = torch.empty(self.info.early_floats, dtype=torch.float32, device=self.device) if early is None \
             else early
@@ -357,20 +392,22 @@ class Plan:
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_forward_early(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                           _ptr(out), _ptr(early), _ptr(start), _ptr(ws), ws.numel(),
-                                           _stream(stream)))
+        _check(lib().framrir_forward_early(self._h, self._ck(desc, "desc"), self._ck(table, "table"),
+                                           self._ck(mic, "mic"), self._ck(src, "src"), self._ck(r, "r"),
+                                           self._ck(out, "out"), self._ck(early, "early"), self._ck(start, "start"),
+                                           self._ck(ws, "ws"), ws.numel(), _stream(stream)))
         return out, table, early, start
 
     def forward_noalloc(self, table, out, mic=None, src=None, r=None, stream=None, desc=None):
         """framrir_forward_noalloc: the forward with the library's static
         device scratch as its workspace (no allocation in the call; the
-        caller passes the table and the output)."""
+        caller passes the table, or None, and the output)."""
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_forward_noalloc(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                             _ptr(out), _stream(stream)))
+        _check(lib().framrir_forward_noalloc(self._h, self._ck(desc, "desc"), self._ck(table, "table"),
+                                             self._ck(mic, "mic"), self._ck(src, "src"), self._ck(r, "r"),
+                                             self._ck(out, "out"), _stream(stream)))
         return out, table
 
     def prepare(self, table, mic=None, src=None, r=None, ws=None, draw=False, stream=None, desc=None):
@@ -379,8 +416,9 @@ class Plan:
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_prepare(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r), int(draw),
-                                     _ptr(ws), ws.numel(), _stream(stream)))
+        _check(lib().framrir_prepare(self._h, self._ck(desc, "desc"), self._ck(table, "table"), self._ck(mic, "mic"),
+                                     self._ck(src, "src"), self._ck(r, "r"), int(draw), self._ck(ws, "ws"), ws.numel(),
+                                     _stream(stream)))
         return ws
 
     def render_prepared(self, table, mic=None, src=None, r=None, out=None, ws=None, stream=None, desc=None):
@@ -389,8 +427,9 @@ class Plan:
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_render_prepared(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                             _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        _check(lib().framrir_render_prepared(self._h, self._ck(desc, "desc"), self._ck(table, "table"),
+                                             self._ck(mic, "mic"), self._ck(src, "src"), self._ck(r, "r"),
+                                             self._ck(out, "out"), self._ck(ws, "ws"), ws.numel(), _stream(stream)))
         return out
 
     def backward(self, table, grad_out, mic=None, src=None, r=None, ws=None, grads=None, stream=None, desc=None,
@@ -411,13 +450,15 @@ class Plan:
                      torch.empty(self.info.n_rooms, dtype=torch.float32, device=self.device))
         gm, gs, gr = grads
         if prepared:
-            _check(lib().framrir_render_backward_prepared(self._h, _ptr(desc), _ptr(mic), _ptr(r), _ptr(grad_out),
-                                                          _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws), ws.numel(),
-                                                          _stream(stream)))
+            _check(lib().framrir_render_backward_prepared(self._h, self._ck(desc, "desc"), self._ck(mic, "mic"),
+                                                          self._ck(r, "r"), self._ck(grad_out, "out"),
+                                                          self._ck(gm, "gm"), self._ck(gs, "gs"), self._ck(gr, "gr"),
+                                                          self._ck(ws, "ws"), ws.numel(), _stream(stream)))
         else:
-            _check(lib().framrir_render_backward(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                                 _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr), _ptr(ws),
-                                                 ws.numel(), _stream(stream)))
+            _check(lib().framrir_render_backward(self._h, self._ck(desc, "desc"), self._ck(table, "table"),
+                                                 self._ck(mic, "mic"), self._ck(src, "src"), self._ck(r, "r"),
+                                                 self._ck(grad_out, "out"), self._ck(gm, "gm"), self._ck(gs, "gs"),
+                                                 self._ck(gr, "gr"), self._ck(ws, "ws"), ws.numel(), _stream(stream)))
         return gm, gs, gr
 
     def backward_draws(self, table, grad_out, ws=None, grads=None, stream=None, desc=None, prepared=False):
@@ -435,13 +476,16 @@ class Plan:
                      torch.empty(self.info.n_rooms, dtype=torch.float32, device=self.device))
         gm, gs, gr = grads
         if prepared:
-            _check(lib().framrir_render_backward_draws_prepared(self._h, _ptr(desc), _ptr(self.mic_dev),
-                                                                _ptr(grad_out), _ptr(gm), _ptr(gs), _ptr(gr),
-                                                                _ptr(ws), ws.numel(), _stream(stream)))
+            _check(lib().framrir_render_backward_draws_prepared(self._h, self._ck(desc, "desc"), _ptr(self.mic_dev),
+                                                                self._ck(grad_out, "out"), self._ck(gm, "gm"),
+                                                                self._ck(gs, "gs"), self._ck(gr, "gr"),
+                                                                self._ck(ws, "ws"), ws.numel(), _stream(stream)))
         else:
-            _check(lib().framrir_render_backward_draws(self._h, _ptr(desc), _ptr(table), _ptr(self.mic_dev),
-                                                       _ptr(self.src_dev), _ptr(grad_out), _ptr(gm), _ptr(gs),
-                                                       _ptr(gr), _ptr(ws), ws.numel(), _stream(stream)))
+            _check(lib().framrir_render_backward_draws(self._h, self._ck(desc, "desc"), self._ck(table, "table"),
+                                                       _ptr(self.mic_dev), _ptr(self.src_dev),
+                                                       self._ck(grad_out, "out"), self._ck(gm, "gm"),
+                                                       self._ck(gs, "gs"), self._ck(gr, "gr"), self._ck(ws, "ws"),
+                                                       ws.numel(), _stream(stream)))
         return gm, gs, gr
 
     def forward_multirate(self, table=None, mic=None, src=None, r=None, inter=None, out=None, ws=None,
@@ -459,8 +503,10 @@ class Plan:
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_forward_multirate(self._h, _ptr(desc), _ptr(table), _ptr(mic), _ptr(src), _ptr(r),
-                                               _ptr(inter), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        _check(lib().framrir_forward_multirate(self._h, self._ck(desc, "desc"), self._ck(table, "table"),
+                                               self._ck(mic, "mic"), self._ck(src, "src"), self._ck(r, "r"),
+                                               self._ck(inter, "inter"), self._ck(out, "out"), self._ck(ws, "ws"),
+                                               ws.numel(), _stream(stream)))
         return out, table, inter
 
     def multirate_filter(self, inter, out=None, ws=None, stream=None, desc=None):
@@ -469,8 +515,8 @@ class Plan:
         out = self.empty_out() if out is None else out
         ws = torch.zeros(self.info.ws_mr_bytes, dtype=torch.uint8, device=self.device) if ws is None else ws
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_multirate_filter(self._h, _ptr(desc), _ptr(inter), _ptr(out), _ptr(ws), ws.numel(),
-                                              _stream(stream)))
+        _check(lib().framrir_multirate_filter(self._h, self._ck(desc, "desc"), self._ck(inter, "inter"),
+                                              self._ck(out, "out"), self._ck(ws, "ws"), ws.numel(), _stream(stream)))
         return out
 
     def spatial_workspace_bytes(self, n_samples):
@@ -508,7 +554,8 @@ class Plan:
         mic = self.mic_dev if mic is None else mic
         src = self.src_dev if src is None else src
         desc = self.desc if desc is None else desc
-        _check(lib().framrir_early(self._h, _ptr(desc), _ptr(mic), _ptr(src), _ptr(out), _ptr(early), _ptr(start),
+        _check(lib().framrir_early(self._h, self._ck(desc, "desc"), self._ck(mic, "mic"), self._ck(src, "src"),
+                                   self._ck(out, "out"), self._ck(early, "early"), self._ck(start, "start"),
                                    _stream(stream)))
         return early, start
 

@@ -258,3 +258,24 @@ def test_handle_without_a_gpu_fails_cleanly():
     with pytest.raises(fr.FramrirError) as e:
         fr.Handle(0, ())
     assert e.value.code in (-1, -5)
+
+
+def test_binding_checks_tensors_before_the_call():
+    """The binding checks dtype, contiguity, element count and device of every
+    tensor it hands to the library, so a float32 position tensor (natural for
+    a learnable parameter) is refused instead of being read as doubles."""
+    import torch
+    from paper_2304_08052_amd import framrir as fr
+    plan = fr.Plan(W.small_mixed(2, seed=3), device="cpu")
+    n_mic = plan.info.n_mic
+    with pytest.raises(TypeError):
+        plan._ck(torch.zeros(3 * n_mic, dtype=torch.float32), "mic")
+    with pytest.raises(ValueError):
+        plan._ck(torch.zeros(3 * n_mic - 1, dtype=torch.float64), "mic")
+    with pytest.raises(ValueError):
+        plan._ck(torch.zeros(6 * n_mic, dtype=torch.float64)[::2], "mic")
+    with pytest.raises(ValueError):   # right dtype and size, but host memory
+        plan._ck(torch.zeros(3 * n_mic, dtype=torch.float64), "mic")
+    with pytest.raises(TypeError):
+        plan._ck(torch.zeros(plan.info.out_floats, dtype=torch.float64), "out")
+    assert plan._ck(None, "r") is None

@@ -44,7 +44,10 @@ def test_forward_noalloc_refuses_large_plans():
     assert plan.info.ws_bytes > fr.NOALLOC_SCRATCH_BYTES
     out = torch.empty(8, dtype=torch.float32, device="cuda")
     table = torch.empty((8, 4), dtype=torch.float64, device="cuda")
+    # straight through the C ABI (the binding would refuse the small buffers
+    # first): the size check comes before anything touches them
     with pytest.raises(fr.FramrirError) as e:
-        plan.forward_noalloc(table, out)
+        fr._check(fr.lib().framrir_forward_noalloc(plan._h, fr._ptr(plan.desc), fr._ptr(table), fr._ptr(plan.mic_dev),
+                                                   fr._ptr(plan.src_dev), None, fr._ptr(out), fr._stream(None)))
     assert e.value.code == -4 and "static scratch" in str(e.value)
     torch.cuda.synchronize()
