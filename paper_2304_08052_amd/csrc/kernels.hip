@@ -2053,8 +2053,9 @@ __device__ __forceinline__ DmStart dm_start_load(__amdgpu_buffer_rsrc_t xv, cons
 // 256, ... (32 samples each), starts at deviation p_j + phi_sub[j] d(k) with
 // its input history from memory, and runs the recurrence over its samples,
 // writing y (0 outside [0, T_l)) over them.  The span is scaled and converted
-// in place to fp16 pairs: elements (2p, 2p+1) become word 2p = their hi
-// halves, word 2p+1 = their lo halves.  Products: the K steps are dealt to
+// in place to fp16 halves: each group of 8 elements (8-aligned) becomes four
+// words of hi halves, then four of lo halves, so that an operand's hi and lo
+// parts are one 16-byte read each.  Products: the K steps are dealt to
 // the four waves in turn; a wave applies each filter fragment it loads to all
 // four 256-output blocks (four independent accumulators), and the partial
 // tiles are summed through LDS in wave order.
@@ -2091,6 +2092,8 @@ __global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu
                 const int woff = static_cast<int>(jb - wb);
                 const int n_sub = (woff + span_len + kHpSub - 1) / kHpSub;
                 const int n_el = n_sub * kHpSub;
+                // the first sub-chunk's start state loads while the window lands
+                DmStart ss = dm_start_load(xv, sub, init, R, ci0, kf, wb, tid, n_sub);
                 __syncthreads();   // the previous tile's reads are done
                 if (tid == 0) s_max = 0;
                 // coalesced load of the window
@@ -2108,8 +2111,6 @@ __global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu
                     }
                 }
                 for (int w = n_el + tid; w < n_el + kHpSub; w += kDmThreads) span[dm_word(w)] = 0.0f;
-                // the first sub-chunk's start state loads while the window lands
-                DmStart ss = dm_start_load(xv, sub, init, R, ci0, kf, wb, tid, n_sub);
                 __syncthreads();
                 float vmax = 0.0f;
                 for (int g = tid; g < n_sub; g += kDmThreads) {
@@ -2144,26 +2145,35 @@ __global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu
                     for (int i = 0; i < kHpSub / 4; ++i) dst[i] = f32x4{xr[4 * i], xr[4 * i + 1], xr[4 * i + 2], xr[4 * i + 3]};
                 }
                 atomicMax(&s_max, __float_as_int(vmax));
-                // the wave's first filter fragments load during the conversion
+                // the wave's first two steps' filter fragments load during the conversion
                 int fl = lane;
                 asm volatile("" : "+v"(fl));
-                u32x4 ah = u32x4{0u, 0u, 0u, 0u}, al = ah;
+                u32x4 ah = u32x4{0u, 0u, 0u, 0u}, al = ah, ahn = ah, aln = ah;   // steps wave and wave + 4
                 if (wave < steps) {
                     ah = *reinterpret_cast<const u32x4*>(fr + (wave * 2 + 0) * 256 + 4 * fl);
                     al = *reinterpret_cast<const u32x4*>(fr + (wave * 2 + 1) * 256 + 4 * fl);
+                }
+                if (wave + kDmBlocks < steps) {
+                    ahn = *reinterpret_cast<const u32x4*>(fr + ((wave + kDmBlocks) * 2 + 0) * 256 + 4 * fl);
+                    aln = *reinterpret_cast<const u32x4*>(fr + ((wave + kDmBlocks) * 2 + 1) * 256 + 4 * fl);
                 }
                 __syncthreads();
                 // scale: the largest input to ~2^14 (fp16 keeps the lo halves normal)
                 const float mx = __int_as_float(s_max);
                 const int ex = mx > 0.0f ? max(-100, (__float_as_int(mx) >> 23) - 127) : 0;
                 const float sc = __int_as_float((127 + 14 - ex) << 23), inv_sc = __int_as_float((127 - 14 + ex) << 23);
-                for (int p = woff / 2 + tid; p < (n_el + kHpSub) / 2; p += kDmThreads) {
-                    float* w = span + dm_word(2 * p);
-                    const float a = w[0] * sc, c = w[1] * sc;
-                    const uint32_t hw = pack_f16(a, c);
-                    const uint32_t lw = pack_f16(a - f16_lo_of(hw), c - f16_hi_of(hw));
-                    reinterpret_cast<uint32_t*>(w)[0] = hw;
-                    reinterpret_cast<uint32_t*>(w)[1] = lw;
+                for (int q = woff / 8 + tid; q < (n_el + kHpSub) / 8; q += kDmThreads) {
+                    // elements 8q .. 8q + 7: four words of hi halves, then four of lo halves
+                    f32x4* w = reinterpret_cast<f32x4*>(span + dm_word(8 * q));
+                    const f32x4 x0 = w[0] * sc, x1 = w[1] * sc;
+                    const u32x4 hw = u32x4{pack_f16(x0.x, x0.y), pack_f16(x0.z, x0.w), pack_f16(x1.x, x1.y),
+                                           pack_f16(x1.z, x1.w)};
+                    const u32x4 lw = u32x4{pack_f16(x0.x - f16_lo_of(hw.x), x0.y - f16_hi_of(hw.x)),
+                                           pack_f16(x0.z - f16_lo_of(hw.y), x0.w - f16_hi_of(hw.y)),
+                                           pack_f16(x1.x - f16_lo_of(hw.z), x1.y - f16_hi_of(hw.z)),
+                                           pack_f16(x1.z - f16_lo_of(hw.w), x1.w - f16_hi_of(hw.w))};
+                    reinterpret_cast<u32x4*>(w)[0] = hw;
+                    reinterpret_cast<u32x4*>(w)[1] = lw;
                 }
                 __syncthreads();
                 // steps wave, wave + 4, ...: column col of block blk starts at
@@ -2171,34 +2181,35 @@ __global__ void __launch_bounds__(kDmThreads) __attribute__((amdgpu_waves_per_eu
                 f32x4 acc[kDmBlocks];
 #pragma unroll
                 for (int blk = 0; blk < kDmBlocks; ++blk) acc[blk] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                const int cb = woff + 16 * col * rl + 8 * grp;
+                // operand words of step st: dm_word(e + 32 st) = dm_word(e) + 36 st
+                const u32x4* bw[kDmBlocks];
+#pragma unroll
+                for (int blk = 0; blk < kDmBlocks; ++blk)
+                    bw[blk] = reinterpret_cast<const u32x4*>(span) +
+                              dm_word(woff + (256 * blk + 16 * col) * rl + 8 * grp + 32 * wave) / 4;
+                constexpr int kStepWords = 36 * kDmBlocks / 4;   // u32x4 per dealt step
                 for (int st = wave; st < steps; st += kDmBlocks) {
-                    u32x4 ahn = ah, aln = al;
-                    if (st + kDmBlocks < steps) {
-                        ahn = *reinterpret_cast<const u32x4*>(fr + ((st + kDmBlocks) * 2 + 0) * 256 + 4 * fl);
-                        aln = *reinterpret_cast<const u32x4*>(fr + ((st + kDmBlocks) * 2 + 1) * 256 + 4 * fl);
+                    u32x4 ahf = ahn, alf = aln;   // two steps ahead
+                    if (st + 2 * kDmBlocks < steps) {
+                        ahf = *reinterpret_cast<const u32x4*>(fr + ((st + 2 * kDmBlocks) * 2 + 0) * 256 + 4 * fl);
+                        alf = *reinterpret_cast<const u32x4*>(fr + ((st + 2 * kDmBlocks) * 2 + 1) * 256 + 4 * fl);
                     }
 #pragma unroll
                     for (int h = 0; h < kDmBlocks; h += 2) {   // two blocks' operands at a time
-                        u32x4 bh[2], bl[2];
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const uint32_t* w =
-                                reinterpret_cast<const uint32_t*>(span) + dm_word(cb + 256 * (h + q) * rl + 32 * st);
-                            const u32x4 w0 = *reinterpret_cast<const u32x4*>(w);
-                            const u32x4 w1 = *reinterpret_cast<const u32x4*>(w + 4);
-                            bh[q] = u32x4{w0[0], w0[2], w1[0], w1[2]};
-                            bl[q] = u32x4{w0[1], w0[3], w1[1], w1[3]};
-                        }
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) acc[h + q] = mfma_16x16x32(ah, bh[q], acc[h + q]);
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) acc[h + q] = mfma_16x16x32(ah, bl[q], acc[h + q]);
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) acc[h + q] = mfma_16x16x32(al, bh[q], acc[h + q]);
+                        const u32x4 bh0 = bw[h][0], bl0 = bw[h][1], bh1 = bw[h + 1][0], bl1 = bw[h + 1][1];
+                        acc[h] = mfma_16x16x32(ah, bh0, acc[h]);
+                        acc[h + 1] = mfma_16x16x32(ah, bh1, acc[h + 1]);
+                        acc[h] = mfma_16x16x32(ah, bl0, acc[h]);
+                        acc[h + 1] = mfma_16x16x32(ah, bl1, acc[h + 1]);
+                        acc[h] = mfma_16x16x32(al, bh0, acc[h]);
+                        acc[h + 1] = mfma_16x16x32(al, bh1, acc[h + 1]);
                     }
+#pragma unroll
+                    for (int blk = 0; blk < kDmBlocks; ++blk) bw[blk] += kStepWords;
                     ah = ahn;
                     al = aln;
+                    ahn = ahf;
+                    aln = alf;
                 }
                 __syncthreads();   // every wave is done with the span: it now holds the partial tiles
                 f32x4* part = reinterpret_cast<f32x4*>(span);
