@@ -85,6 +85,22 @@ def measured_spatial_traffic():
     return int(kv["traffic_bytes"])
 
 
+MULTIRATE_PROFILE = os.path.join(HERE, "profiles", "kernels_multirate256_trace.md")
+
+
+def measured_multirate_traffic():
+    """HBM bytes of the multi-rate filter stages on the batched workload from
+    the committed counter passes, or None when the kernel sources differ."""
+    try:
+        with open(MULTIRATE_PROFILE) as f:
+            kv = dict(line.split(" = ", 1) for line in f.read().splitlines() if " = " in line)
+    except OSError:
+        return None
+    if kv.get("workload") != "multirate" or kv.get("source_sha256") != kernel_sources_sha256():
+        return None
+    return int(kv["traffic_bytes"])
+
+
 def launch_key(launch):
     """The launch shape as the counter summaries record it."""
     keys = ["lds_bytes", "wg_threads", "grid_wgs", "max_mic_group", "waves_per_simd"]
@@ -678,6 +694,8 @@ def run_multirate(args, batch, desc, launch):
     table, out = plan.empty_table(), plan.empty_out()
     inter = torch.empty(info.mr_floats, dtype=torch.float32, device="cuda")
     ws = torch.zeros(info.ws_mr_bytes, dtype=torch.uint8, device="cuda")
+    if args.copy_probe_mb > 0:
+        copy_probe(args.copy_probe_mb)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -729,6 +747,8 @@ def run_multirate(args, batch, desc, launch):
     # filter stages: the intermediate signal read twice (chunk-end states, then
     # the decimation windows) and the output written once
     filter_bytes = 4.0 * (2 * int(info.mr_floats) + int(info.out_floats))
+    # the counter traffic is for the batched workload only
+    mr_traffic = measured_multirate_traffic() if int(info.n_rooms) == 256 else None
     achieved = filter_bytes / (filter_ms * 1e-3) / 1e9
     line = {
         "metric": "multi-channel RIRs/sec, paper-literal multi-rate rendering, batch 256, 16 kHz",
@@ -739,7 +759,9 @@ def run_multirate(args, batch, desc, launch):
                    "intermediate_samples": int(info.mr_floats), "samples_out": int(info.out_floats),
                    "launch": plan.launch},
         "roofline": {"bound": "hbm", "kernel": "hp_chunk_end + hp_carry + decimate_mfma", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": mr_traffic,
+                     "traffic_over_algorithmic": mr_traffic / filter_bytes if mr_traffic else None,
+                     "traffic_source": os.path.relpath(MULTIRATE_PROFILE, HERE) if mr_traffic else None,
                      "algorithmic_bytes": filter_bytes, "filter_ms": filter_ms,
                      "decimation_flops": dec_flops,
                      "decimation_flops_rate_tflops": dec_flops / (filter_ms * 1e-3) / 1e12},
