@@ -108,3 +108,24 @@ def spatial_errors(job):
     e_mix = max(rel_l2(np.asarray(mix[m], dtype=np.float64), want_mix[m]) for m in range(M))
     e_g = float(np.max(np.abs(np.asarray(g, dtype=np.float64) - want_g) / want_g))
     return e_img, e_mix, e_g
+
+
+def multirate_errors(job):
+    """job = (one-room batch, GPU intermediate signal [S, M, T_l], GPU output
+    [S, M, T]): the worst per-channel relative L2 errors of both against the
+    multi-rate oracle (Sec. II, Eq. 7-8), the output taken through the
+    oracle's high-pass and decimation of its own intermediate signal."""
+    from oracle import multirate as M
+    one, got_l, got = job
+    F, rm, op = _room(one)
+    want_l = M.intermediate_room(op, rm)
+    _, _, t_len = M.lengths(rm.rt60, rm.fs)
+    got_l = np.asarray(got_l, dtype=np.float64).reshape(want_l.shape)
+    got = np.asarray(got, dtype=np.float64).reshape(want_l.shape[0], want_l.shape[1], t_len)
+    e1 = e3 = 0.0
+    for s in range(want_l.shape[0]):
+        for m in range(want_l.shape[1]):
+            e1 = max(e1, rel_l2(got_l[s, m], want_l[s, m]))
+            want = M.decimate(M.highpass(want_l[s, m], rm.fs), rm.fs, t_len)
+            e3 = max(e3, rel_l2(got[s, m], want))
+    return e1, e3

@@ -114,3 +114,34 @@ def test_multirate_reproducible_and_single_rate_calls_refused():
         plan.forward()
     with pytest.raises(fr.FramrirError):
         plan.backward(plan.empty_table(), torch.zeros(plan.info.out_floats, device="cuda"))
+
+
+def test_multirate_every_room_of_the_batched_workload(oracle_pool):
+    """Every room of the 256-room batch through the multi-rate chain, in the
+    tuned launch shape, against the oracle (worker processes forked before
+    the GPU was used): both the intermediate signal and the output, worst
+    channel of each room at 1e-5."""
+    import torch
+    from paper_2304_08052_amd import autotune
+    from paper_2304_08052_amd import framrir as fr
+    from tests import oracle_pool as P
+    batch = W.config2()
+    plan = fr.Plan(batch, launch=autotune.launch_for(batch), multirate=True)
+    say("multi-rate, every room of the 256-room batch")
+    out, table, inter = plan.forward_multirate()
+    torch.cuda.synchronize()
+    out, inter = out.cpu().numpy(), inter.cpu().numpy()
+    ones = fr.split_rooms(batch)
+    jobs, off = [], 0
+    for b, rm in enumerate(F.rooms_from_batch(batch)):
+        _, t_l, _ = M.lengths(rm.rt60, rm.fs)
+        n = len(rm.src) * len(rm.mic) * t_l
+        jobs.append((ones[b], inter[off:off + n], out[plan.out_off[b]:plan.out_off[b + 1]]))
+        off += n
+    assert off == plan.info.mr_floats
+    res = oracle_pool.map(P.multirate_errors, jobs, chunksize=1)
+    e1 = np.array([r[0] for r in res])
+    e3 = np.array([r[1] for r in res])
+    say(f"multi-rate every room: intermediate worst {e1.max():.2e} (room {int(e1.argmax())}), "
+        f"output worst {e3.max():.2e} (room {int(e3.argmax())}), output median {np.median(e3):.2e}")
+    assert e1.max() <= RIR_TOL and e3.max() <= RIR_TOL
