@@ -13,6 +13,19 @@
 //                    (or, DRAWS, with the images moving with the inputs):
 //                    per pair 81-tap dot products of dL/dh with P and P', and
 //                    the fixed-order reduction of each room's partials.
+//   render_moment_kernel  the second render path: per pair six moments and
+//                    five centre taps into LDS bins, then a Toeplitz FIR over
+//                    the bins on the fp16 matrix cores.
+//   early_kernel     Eq. 9: the early-reverberation window of each channel
+//                    (the render's EARLY instances store the same windows
+//                    from the writeback).
+//   hp_chunk_end_kernel, hp_carry_kernel, dec_frag_kernel,
+//   decimate_mfma_kernel  Sec. II, the multi-rate chain after the render:
+//                    the 80 Hz high-pass's states at every 32-sample
+//                    sub-chunk, then the decimation by r_l as a Toeplitz
+//                    product on the matrix cores, re-running the high-pass
+//                    over each tile's window.
+// The spatialisation kernels are in spatial.hip.
 //
 // Compiled with -ffp-contract=off: FP64 draw arithmetic is rounded one
 // operation at a time, in the order the method states.  FMAs in the render
