@@ -221,15 +221,35 @@ def _oracle_rooms(sub):
 
 
 def host_cpu_model():
-    """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
+    """The host CPU as /proc/cpuinfo names it (model name, family / model /
+    stepping, clock), with the logical CPUs of the machine and of this
+    process's CPU set, or None."""
     try:
         with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+            text = f.read()
     except OSError:
-        pass
-    return None
+        return None
+    first = text.split("\n\n", 1)[0]
+    kv = {}
+    for line in first.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    name = kv.get("model name")
+    if name is None:
+        return None
+    n_cpu = text.count("processor\t:") or text.count("processor :")
+    try:
+        n_set = len(os.sched_getaffinity(0))
+    except OSError:
+        n_set = n_cpu
+    parts = [name]
+    if "cpu family" in kv and "model" in kv:
+        parts.append(f"family {kv['cpu family']} model {kv['model']} stepping {kv.get('stepping', '?')}")
+    if "cpu MHz" in kv:
+        parts.append(f"{float(kv['cpu MHz']):.0f} MHz")
+    parts.append(f"{n_cpu} logical CPUs, {n_set} in this process's CPU set")
+    return ", ".join(parts)
 
 
 def cpu_baseline(batch, n_rooms):
