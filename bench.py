@@ -152,8 +152,8 @@ def measured_valu_insts(workload_name, launch):
 def parse_args():
     p = argparse.ArgumentParser(description=__doc__)
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=100)
-    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="batched", choices=["batched", "long", "mixed", "one", "multirate",
                                                               "spatial"])
     p.add_argument("--cpu-rooms", type=int, default=256,
@@ -474,6 +474,11 @@ def main():
     value = n_rirs / (step_ms * 1e-3)
     achieved = taps * FLOPS_PER_TAP / (render_ms * 1e-3) / 1e12
     cpu = cpu_baseline(batch, args.cpu_rooms) if args.cpu_rooms > 0 else None
+    cpu_long_1 = None
+    if args.cpu_rooms > 0 and args.workload == "batched":   # the long-filter workload in full, one core
+        long_batch, _ = workload("long")
+        cpu_long_1 = cpu_baseline(long_batch, len(long_batch["rt60"]))
+        cpu_long_1["workload"] = "long filters: 64 rooms, 48 kHz, 8 mics, T60 0.6-1.2 s"
     traffic = measured_traffic(args.workload, plan.launch)
     step_traffic = measured_step_traffic(args.workload, plan.launch)
     insts = measured_valu_insts(args.workload, plan.launch)
@@ -554,6 +559,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_par,
+        "cpu_baseline_long_filters": cpu_long_1,
         "cpu_baseline_long_filters_all_cores": cpu_long,
         "eager_ms_per_step": eager_ms,
         "eager_ms_p10_p50_p90": pct(eager_each),
