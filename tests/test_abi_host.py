@@ -279,3 +279,18 @@ def test_binding_checks_tensors_before_the_call():
     with pytest.raises(TypeError):
         plan._ck(torch.zeros(plan.info.out_floats, dtype=torch.float64), "out")
     assert plan._ck(None, "r") is None
+
+
+@pytest.mark.parametrize("fs,ok", [(5000.0, False), (6000.0, True), (192000.0, True), (300000.0, False)])
+def test_multirate_decimation_ratio_range(fs, ok):
+    """A multi-rate plan takes 1 < r_l <= 12 (r_l = floor(sqrt(floor(10^6 / fs))),
+    Sec. II): 6 kHz (r_l = 12) and 192 kHz (r_l = 2) are planned, 5 kHz
+    (r_l = 14) and 300 kHz (r_l = 1) are refused with the range code."""
+    batch = _bad(W.config1(), fs=np.array([fs]))
+    if ok:
+        plan = fr.Plan(batch, multirate=True, device="cpu")
+        assert plan.info.mr_floats > 0
+    else:
+        with pytest.raises(fr.FramrirError) as ei:
+            fr.Plan(batch, multirate=True, device="cpu")
+        assert ei.value.code == -3 and "r_l" in str(ei.value)

@@ -145,3 +145,21 @@ def test_multirate_every_room_of_the_batched_workload(oracle_pool):
     say(f"multi-rate every room: intermediate worst {e1.max():.2e} (room {int(e1.argmax())}), "
         f"output worst {e3.max():.2e} (room {int(e3.argmax())}), output median {np.median(e3):.2e}")
     assert e1.max() <= RIR_TOL and e3.max() <= RIR_TOL
+
+
+def test_multirate_every_decimation_ratio():
+    """One room per r_l from 2 to 12 (6 kHz .. 192 kHz): each r_l has its own
+    fragment table, filter half-length, window pad and step count in the
+    decimation kernel, so every one the plan accepts apart from the 16 and
+    48 kHz rooms above (r_l = 7 and 4) is rendered here against the oracle."""
+    import torch
+    from paper_2304_08052_amd import framrir as fr
+    fss = (6000.0, 8000.0, 11025.0, 22050.0, 32000.0, 96000.0, 192000.0)
+    batch = W.small_mixed(len(fss), seed=31, fs_choices=(16000.0,), rt60_range=(0.06, 0.15))
+    batch["fs"] = np.array(fss)
+    assert sorted(M.rate_factors(f)[1] for f in fss) == [2, 3, 5, 6, 9, 11, 12]
+    plan = fr.Plan(batch, multirate=True)
+    say("multi-rate, r_l = 2 .. 12")
+    out, table, inter = plan.forward_multirate()
+    torch.cuda.synchronize()
+    _check_rooms(batch, plan, out, inter, range(len(fss)))
