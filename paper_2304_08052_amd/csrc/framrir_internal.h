@@ -59,6 +59,16 @@ struct DescHeader {
     int32_t max_out_tiles;     // decimation tiles per channel, at most
     int32_t max_rl;
     int64_t src_order_bytes;   // byte offset of int32[n_src]: the sources by row count, largest first
+    int64_t hp_task_bytes;     // byte offset of HpTask[n_hp_tasks] (multi-rate plans)
+    int32_t n_hp_tasks;        // high-pass blocks of kHpEndChunks chunks over all channels
+    int32_t pad_hp;
+};
+
+// One block of the high-pass state pass: kHpEndChunks consecutive chunks of
+// one channel (room b, channel chan = s n_mic + m of the room, first chunk
+// kHpEndChunks blk).
+struct HpTask {
+    int32_t room, chan, blk;
 };
 
 struct RoomDesc {
@@ -88,6 +98,7 @@ struct RoomDesc {
 };
 
 constexpr int kHpChunk = 256;         // intermediate samples per high-pass chunk
+constexpr int kHpEndChunks = 32;      // chunks per block of the high-pass state pass
 constexpr int kHpSub = 32;            // samples per sub-chunk (one thread's run of the recursion)
 constexpr int kMaxRl = 12;            // largest r_l a multi-rate plan accepts
 // Decimation on the matrix cores: a workgroup of kDmThreads takes kDmBlocks
@@ -135,6 +146,9 @@ FR_HD const int32_t* room_items(const void* blob) {
 }
 FR_HD const int32_t* src_order(const void* blob) {
     return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(blob) + hdr(blob)->src_order_bytes);
+}
+FR_HD const HpTask* hp_tasks(const void* blob) {
+    return reinterpret_cast<const HpTask*>(reinterpret_cast<const char*>(blob) + hdr(blob)->hp_task_bytes);
 }
 
 // ---------------------------------------------------------------------------

@@ -1844,73 +1844,96 @@ __device__ __forceinline__ double2 hp_sub_partial(const float (&xr)[kHpSub], dou
 // over the banks.
 __device__ __forceinline__ int hp_word(int w) { return w + (w >> 5); }
 
-constexpr int kHpEndChunks = 32;                         // chunks per hp_chunk_end_kernel block
 constexpr int kHpSubPerChunk = kHpChunk / kHpSub;        // 8
+constexpr int kHpEndGrid = 1024;                         // persistent workgroups of hp_chunk_end_kernel
 constexpr int kHpEndThreads = kHpEndChunks * kHpSubPerChunk;
 static_assert(kHpEndThreads == 256 && kHpSub == 32, "one sub-chunk per thread, 32 chunks per block");
 
-// Partial deviations of every chunk: block = 32 consecutive chunks of a
-// channel (8192 samples, loaded coalesced into LDS), thread = sub-chunk; the
-// sub-chunk end deviations e_j are combined in order by one thread per chunk,
-// p_0 = 0, p_(j+1) = e_j + phi_sub[1] p_j: p_j to sub (one per sub-chunk), p_8
-// = e(k) to zend.  Blocks: (chunks / 32, rooms, channels).
+// Partial deviations of every chunk: a task is a block of 32 consecutive
+// chunks of a channel (8192 samples, loaded coalesced into LDS); thread =
+// sub-chunk; the sub-chunk end deviations e_j are combined in order by one
+// thread per chunk, p_0 = 0, p_(j+1) = e_j + phi_sub[1] p_j: p_j to sub (one
+// per sub-chunk), p_8 = e(k) to zend.  The grid is persistent over the plan's
+// task list: while a block runs its recursion, the next block's samples are
+// already in flight, so the loads never wait on a descriptor chain or an idle
+// workgroup.
 __global__ void __launch_bounds__(kHpEndThreads) hp_chunk_end_kernel(const void* __restrict__ desc,
                                                                      const float* __restrict__ x,
                                                                      double* __restrict__ zend,
                                                                      double2* __restrict__ sub) {
     constexpr int kSamples = kHpEndChunks * kHpChunk;
+    constexpr int kPer = kSamples / kHpEndThreads;     // samples per thread and block
     __shared__ float xs[kSamples + kSamples / 32];
     __shared__ double2 es[kHpEndThreads];
     const DescHeader* H = hdr(desc);
+    const HpTask* tasks = hp_tasks(desc);
+    const int n_tasks = H->n_hp_tasks;
     const int tid = threadIdx.x;
-    for (int b = blockIdx.y; b < H->n_rooms; b += gridDim.y) {
-        const RoomDesc* R = rooms(desc) + b;
-        const int c0 = blockIdx.x * kHpEndChunks;
-        if (c0 >= R->n_chunks) continue;
-        const double b0 = R->hp_b0, a1 = R->hp_a1, a2 = R->hp_a2;
-        for (int local = blockIdx.z; local < R->n_src * R->n_mic; local += gridDim.z) {
-            const __amdgpu_buffer_rsrc_t xv = buffer_view(x + R->out_off + static_cast<int64_t>(local) * R->T, R->T);
-            const int64_t s0 = static_cast<int64_t>(c0) * kHpChunk;   // first sample of the block
-            float v[kSamples / kHpEndThreads];
+    int t = blockIdx.x;
+    if (t >= n_tasks) return;
+    // a block's samples in registers, coalesced (thread 0 also the two before
+    // the block: the input history of its first sub-chunk; 0 before the start)
+    float v[kPer];
+    float h1 = 0.0f, h2 = 0.0f;
+    auto fetch = [&](int task) {
+        const HpTask k = tasks[task];
+        const RoomDesc* R = rooms(desc) + k.room;
+        const __amdgpu_buffer_rsrc_t xv = buffer_view(x + R->out_off + static_cast<int64_t>(k.chan) * R->T, R->T);
+        const int64_t s0 = static_cast<int64_t>(k.blk) * kSamples;
 #pragma unroll
-            for (int q = 0; q < kSamples / kHpEndThreads; ++q) v[q] = view_load(xv, s0 + tid + kHpEndThreads * q);
-            __syncthreads();   // the previous channel's reads are done
-#pragma unroll
-            for (int q = 0; q < kSamples / kHpEndThreads; ++q) xs[hp_word(tid + kHpEndThreads * q)] = v[q];
-            __syncthreads();
-            const int w0 = kHpSub * tid;
-            double x1, x2;
-            if (tid == 0) {
-                x1 = view_load(xv, s0 - 1);
-                x2 = view_load(xv, s0 - 2);
-            } else {
-                x1 = xs[hp_word(w0 - 1)];
-                x2 = xs[hp_word(w0 - 2)];
-            }
-            float xr[kHpSub];
-#pragma unroll
-            for (int i = 0; i < kHpSub; ++i) xr[i] = xs[hp_word(w0 + i)];
-            es[tid] = hp_sub_partial(xr, x1, x2, b0, a1, a2);
-            __syncthreads();
-            const int64_t ci0 = R->chunk0 + static_cast<int64_t>(local) * R->n_chunks + c0;   // the block's first chunk
-            const int c = c0 + tid;
-            if (tid < kHpEndChunks && c < R->n_chunks) {
-                const double* ph = R->phi_sub[1];
-                double d0 = 0.0, d1 = 0.0;
-                for (int j = 0; j < kHpSubPerChunk; ++j) {
-                    const double2 e = es[kHpSubPerChunk * tid + j];
-                    es[kHpSubPerChunk * tid + j] = double2{d0, d1};
-                    const double n0 = e.x + (ph[0] * d0 + ph[1] * d1);
-                    const double n1 = e.y + (ph[2] * d0 + ph[3] * d1);
-                    d0 = n0;
-                    d1 = n1;
-                }
-                zend[2 * (ci0 + tid)] = d0;
-                zend[2 * (ci0 + tid) + 1] = d1;
-            }
-            __syncthreads();
-            if (c0 + tid / kHpSubPerChunk < R->n_chunks) sub[kHpSubPerChunk * ci0 + tid] = es[tid];
+        for (int q = 0; q < kPer; ++q) v[q] = view_load(xv, s0 + tid + kHpEndThreads * q);
+        if (tid == 0) {
+            h1 = view_load(xv, s0 - 1);
+            h2 = view_load(xv, s0 - 2);
         }
+    };
+    fetch(t);
+    for (;;) {
+        const HpTask k = tasks[t];
+        const RoomDesc* R = rooms(desc) + k.room;
+        const int c0 = k.blk * kHpEndChunks;
+        __syncthreads();   // the previous block's reads of xs and es are done
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) xs[hp_word(tid + kHpEndThreads * q)] = v[q];
+        const double hx1 = h1, hx2 = h2;
+        __syncthreads();
+        const int tn = t + static_cast<int>(gridDim.x);
+        if (tn < n_tasks) fetch(tn);   // the next block streams in during this one's recursion
+        const double b0 = R->hp_b0, a1 = R->hp_a1, a2 = R->hp_a2;
+        const int w0 = kHpSub * tid;
+        double x1, x2;
+        if (tid == 0) {
+            x1 = hx1;
+            x2 = hx2;
+        } else {
+            x1 = xs[hp_word(w0 - 1)];
+            x2 = xs[hp_word(w0 - 2)];
+        }
+        float xr[kHpSub];
+#pragma unroll
+        for (int i = 0; i < kHpSub; ++i) xr[i] = xs[hp_word(w0 + i)];
+        es[tid] = hp_sub_partial(xr, x1, x2, b0, a1, a2);
+        __syncthreads();
+        const int64_t ci0 = R->chunk0 + static_cast<int64_t>(k.chan) * R->n_chunks + c0;   // the block's first chunk
+        const int c = c0 + tid;
+        if (tid < kHpEndChunks && c < R->n_chunks) {
+            const double* ph = R->phi_sub[1];
+            double d0 = 0.0, d1 = 0.0;
+            for (int j = 0; j < kHpSubPerChunk; ++j) {
+                const double2 e = es[kHpSubPerChunk * tid + j];
+                es[kHpSubPerChunk * tid + j] = double2{d0, d1};
+                const double n0 = e.x + (ph[0] * d0 + ph[1] * d1);
+                const double n1 = e.y + (ph[2] * d0 + ph[3] * d1);
+                d0 = n0;
+                d1 = n1;
+            }
+            zend[2 * (ci0 + tid)] = d0;
+            zend[2 * (ci0 + tid) + 1] = d1;
+        }
+        __syncthreads();
+        if (c0 + tid / kHpSubPerChunk < R->n_chunks) sub[kHpSubPerChunk * ci0 + tid] = es[tid];
+        if (tn >= n_tasks) break;
+        t = tn;
     }
 }
 
@@ -2736,10 +2759,12 @@ extern "C" int framrir_multirate_filter(const framrir_plan* plan, const void* de
     double* init = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + plan->ws_init_off);
     const unsigned gy = static_cast<unsigned>(std::min(H.n_rooms, 65535));
     const unsigned gz = static_cast<unsigned>(std::min(H.max_room_chan, 65535));
-    const unsigned gc = static_cast<unsigned>((H.max_chunks + kHpEndChunks - 1) / kHpEndChunks);
     double2* sub = reinterpret_cast<double2*>(static_cast<char*>(ws_dev) + plan->ws_sub_off);
-    hipLaunchKernelGGL(hp_chunk_end_kernel, dim3(gc, gy, gz), dim3(kHpEndThreads), 0, st, desc_dev, inter_dev, zend, sub);
-    if ((rc = check_launch("hp_chunk_end_kernel"))) return rc;
+    if (H.n_hp_tasks > 0) {   // persistent: about four workgroups per CU
+        const unsigned g = static_cast<unsigned>(std::min(H.n_hp_tasks, kHpEndGrid));
+        hipLaunchKernelGGL(hp_chunk_end_kernel, dim3(g), dim3(kHpEndThreads), 0, st, desc_dev, inter_dev, zend, sub);
+        if ((rc = check_launch("hp_chunk_end_kernel"))) return rc;
+    }
     hipLaunchKernelGGL(hp_carry_kernel, dim3(gy), dim3(64), 0, st, desc_dev, zend, init);
     if ((rc = check_launch("hp_carry_kernel"))) return rc;
     uint32_t* frag = reinterpret_cast<uint32_t*>(static_cast<char*>(ws_dev) + plan->ws_taps_off);

@@ -482,7 +482,19 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     for (int32_t s = 0; s < src_row; ++s) src_ord[s] = s;
     std::stable_sort(src_ord.begin(), src_ord.end(), [&](int32_t x, int32_t y) { return sd[x].n_img > sd[y].n_img; });
     H.src_order_bytes = align(H.room_items_bytes + static_cast<int64_t>(sizeof(int32_t)) * plan->room_items.size());
-    const int64_t total = align(H.src_order_bytes + static_cast<int64_t>(sizeof(int32_t)) * src_ord.size());
+    // the high-pass state pass of a multi-rate plan: one task per block of
+    // kHpEndChunks chunks of a channel, channel after channel
+    std::vector<HpTask> hp;
+    if (multirate) {
+        for (int32_t b = 0; b < n_rooms; ++b) {
+            const int n_blk = (rd[b].n_chunks + kHpEndChunks - 1) / kHpEndChunks;
+            for (int ch = 0; ch < rd[b].n_src * rd[b].n_mic; ++ch)
+                for (int k = 0; k < n_blk; ++k) hp.push_back(HpTask{b, ch, k});
+        }
+    }
+    H.n_hp_tasks = static_cast<int32_t>(hp.size());
+    H.hp_task_bytes = align(H.src_order_bytes + static_cast<int64_t>(sizeof(int32_t)) * src_ord.size());
+    const int64_t total = align(H.hp_task_bytes + static_cast<int64_t>(sizeof(HpTask)) * hp.size());
     plan->blob.assign(static_cast<size_t>(total), 0);
     char* base = plan->blob.data();
     std::memcpy(base, &H, sizeof(H));
@@ -491,6 +503,7 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     std::memcpy(base + H.item_bytes, it.data(), sizeof(WorkItem) * it.size());
     std::memcpy(base + H.room_items_bytes, plan->room_items.data(), sizeof(int32_t) * plan->room_items.size());
     std::memcpy(base + H.src_order_bytes, src_ord.data(), sizeof(int32_t) * src_ord.size());
+    if (!hp.empty()) std::memcpy(base + H.hp_task_bytes, hp.data(), sizeof(HpTask) * hp.size());
     plan->header = H;
 
     // ---- workspace
