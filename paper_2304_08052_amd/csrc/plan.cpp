@@ -481,6 +481,11 @@ extern "C" int framrir_plan_create(const framrir_room* rooms_in, int32_t n_rooms
     std::vector<int32_t> src_ord(src_row);
     for (int32_t s = 0; s < src_row; ++s) src_ord[s] = s;
     std::stable_sort(src_ord.begin(), src_ord.end(), [&](int32_t x, int32_t y) { return sd[x].n_img > sd[y].n_img; });
+    // When every source's workgroup is resident at once (two per CU), the
+    // dispatcher puts workgroups i and i + kCus on one CU, where they share the
+    // VALU for the draws: the second half of the order is then reversed, so
+    // that the j-th largest source shares its CU with the j-th smallest.
+    if (src_row > kCus && src_row <= 2 * kCus) std::reverse(src_ord.begin() + kCus, src_ord.end());
     H.src_order_bytes = align(H.room_items_bytes + static_cast<int64_t>(sizeof(int32_t)) * plan->room_items.size());
     // the high-pass state pass of a multi-rate plan: one task per block of
     // kHpEndChunks chunks of a channel, channel after channel

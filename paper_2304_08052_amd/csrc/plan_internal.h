@@ -12,6 +12,9 @@
 // static scratch.
 constexpr int kLdsPerCu = 163840;
 constexpr int kMaxDynLdsBytes = 160000;
+// Compute units of an MI355X (gfx950): only the order in which the
+// preparation takes the sources depends on it.
+constexpr int kCus = 256;
 
 // Compiled (threads per workgroup, waves per SIMD) shapes of the render and
 // backward kernels.
