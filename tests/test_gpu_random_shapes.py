@@ -3,8 +3,9 @@ kHz (the rates the other tests leave out included), 1 to 8 microphones, 1 to 3
 sources, T60 from 0.05 s (400 samples at 8 kHz) to 0.9 s, in the tuned launch
 shape and in a small-tile shape that time-tiles every room.  Every room's
 forward per channel within 1e-5 relative L2 and its adjoint (dL/dmic, dL/dsrc,
-dL/dr, draws held fixed) within 1e-4 of the FP64 oracle (Eq. 1-6; the oracle
-runs in the worker pool forked before the GPU is touched)."""
+dL/dr, draws held fixed) within 1e-4 of the FP64 oracle (Eq. 1-6), and half of
+the batches through the multi-rate chain as well (Sec. II, Eq. 7-8).  The oracle
+runs in the worker pool forked before the GPU is touched."""
 import numpy as np
 import pytest
 
@@ -33,3 +34,33 @@ def test_random_shapes_forward_backward(seed, oracle_pool):
     if launch is not None:
         assert plan.info.n_items > 2 * plan.n_rooms   # the small tiles split the rooms in time
     check_jobs(oracle_pool, jobs_for(batch, plan, range(plan.n_rooms), out, G, gm, gs, gr), f"random seed {seed}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_shapes_multirate(seed, oracle_pool):
+    """The same batches through the paper-literal multi-rate chain (Sec. II,
+    Eq. 7-8): intermediate signal and output per channel within 1e-5."""
+    import torch
+    from oracle import framrir as F
+    from oracle import multirate as M
+    from paper_2304_08052_amd import framrir as fr
+    from tests import oracle_pool as P
+    batch = random_batch(seed)
+    plan = fr.Plan(batch, multirate=True)
+    say(f"seed {seed}: multi-rate, rates {[int(f) for f in batch['fs']]}")
+    out, table, inter = plan.forward_multirate()
+    torch.cuda.synchronize()
+    out, inter = out.cpu().numpy(), inter.cpu().numpy()
+    ones = fr.split_rooms(batch)
+    jobs, off = [], 0
+    for b, rm in enumerate(F.rooms_from_batch(batch)):
+        _, t_l, _ = M.lengths(rm.rt60, rm.fs)
+        n = len(rm.src) * len(rm.mic) * t_l
+        jobs.append((ones[b], inter[off:off + n], out[plan.out_off[b]:plan.out_off[b + 1]]))
+        off += n
+    assert off == plan.info.mr_floats
+    res = oracle_pool.map(P.multirate_errors, jobs, chunksize=1)
+    e1 = np.array([r[0] for r in res])
+    e3 = np.array([r[1] for r in res])
+    say(f"seed {seed}: intermediate worst {e1.max():.2e}, output worst {e3.max():.2e}")
+    assert e1.max() <= 1e-5 and e3.max() <= 1e-5
