@@ -1,11 +1,12 @@
 """GPU parity on seeded random batches of unusual shapes: sample rates 8 to 48
 kHz (the rates the other tests leave out included), 1 to 8 microphones, 1 to 3
 sources, T60 from 0.05 s (400 samples at 8 kHz) to 0.9 s, in the tuned launch
-shape and in a small-tile shape that time-tiles every room.  Every room's
-forward per channel within 1e-5 relative L2 and its adjoint (dL/dmic, dL/dsrc,
-dL/dr, draws held fixed) within 1e-4 of the FP64 oracle (Eq. 1-6), and half of
-the batches through the multi-rate chain as well (Sec. II, Eq. 7-8).  The oracle
-runs in the worker pool forked before the GPU is touched."""
+shape, in a small-tile shape that time-tiles every room and in the second
+render path (bin moments).  Every room's forward per channel within 1e-5
+relative L2 and its adjoint (dL/dmic, dL/dsrc, dL/dr, draws held fixed) within
+1e-4 of the FP64 oracle (Eq. 1-6), and half of the batches through the
+multi-rate chain as well (Sec. II, Eq. 7-8).  The oracle runs in the worker
+pool forked before the GPU is touched."""
 import numpy as np
 import pytest
 
@@ -16,6 +17,8 @@ pytestmark = pytest.mark.gpu
 
 FS = (8000.0, 11025.0, 16000.0, 22050.0, 32000.0, 44100.0, 48000.0)
 SMALL_TILES = dict(lds_bytes=16384, wg_threads=256, grid_wgs=0, max_mic_group=2, waves_per_simd=4)
+# the second render path (bin moments, matrix-core pulse filter)
+MOMENTS = dict(lds_bytes=65536, wg_threads=512, grid_wgs=0, max_mic_group=2, waves_per_simd=4, render_path=1)
 
 
 def random_batch(seed):
@@ -23,15 +26,15 @@ def random_batch(seed):
     return W._uca_rooms(4, rng, (1, 3), (1, 8), (0.05, 0.9), FS, seed0=100 * seed)
 
 
-@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("seed", range(10))
 def test_random_shapes_forward_backward(seed, oracle_pool):
     batch = random_batch(seed)
-    launch = SMALL_TILES if seed % 2 else None
+    launch = MOMENTS if seed >= 8 else SMALL_TILES if seed % 2 else None
     shapes = [(int(batch["fs"][b]), int(batch["n_mic"][b]), int(batch["n_src"][b]), round(float(batch["rt60"][b]), 2))
               for b in range(len(batch["rt60"]))]
     say(f"seed {seed}: rooms (fs, mics, sources, T60) {shapes}, launch {launch or 'tuned'}")
     plan, out, G, gm, gs, gr = run_batched(batch, seed=40 + seed, launch=launch)
-    if launch is not None:
+    if launch is SMALL_TILES:
         assert plan.info.n_items > 2 * plan.n_rooms   # the small tiles split the rooms in time
     check_jobs(oracle_pool, jobs_for(batch, plan, range(plan.n_rooms), out, G, gm, gs, gr), f"random seed {seed}")
 
